@@ -1,0 +1,186 @@
+/*
+ * acr.h -- C ABI of the accelerated cyclic reduction (ACR) library for
+ * AMD MI355X (gfx950).
+ *
+ * Method (Chavez, Turkiyyah, Zampini, Keyes, "Parallel accelerated cyclic
+ * reduction preconditioner for three-dimensional elliptic PDEs with
+ * variable coefficients"):
+ *   - Sec. 4.1: block cyclic reduction (red/black ordering of the grid
+ *     planes, block Gaussian elimination without pivoting, recursive
+ *     halving, forward/backward substitution);
+ *   - Sec. 4.2: every plane block held as an H-matrix built on a planar
+ *     bisection cluster tree (Sec. 3.1) with standard admissibility
+ *     (eq. admis) and leaf size n_min;
+ *   - Sec. 4.3: tuning parameters eps (block-wise relative accuracy of
+ *     the low-rank blocks and of the H-arithmetic), eta, n_min;
+ *   - Sec. 5.3, 7, 8: use as a preconditioner of CG / GMRES to a 1e-8
+ *     relative residual.
+ *
+ * Conventions shared by every call
+ *   - Grid: nx, ny, nz interior nodes on the unit cube, h_d = 1/(n_d+1),
+ *     Dirichlet zero boundary.  Unknown p = i + nx*(j + ny*k), x fastest;
+ *     a plane is a fixed k.  N = nx*ny*nz.
+ *   - Node-grid fields (kappa, c, gradients) have (nz+2)*(ny+2)*(nx+2)
+ *     entries, x fastest, boundary layer included.
+ *   - All vector/field pointers are DEVICE pointers (hipMalloc'd or torch
+ *     CUDA tensors) of doubles unless stated otherwise; the caller owns
+ *     them.  The handle owns everything it allocates.
+ *   - Work is ordered on the given stream (0 = the default stream).  Only
+ *     acr_setup and krylov_solve block the host.  Handles are not
+ *     thread-safe.
+ *   - Every call returns an acr_status; no C++ exception crosses the ABI.
+ *     Arguments are validated on the host before any device work; on
+ *     failure *out handles are set to NULL and partial allocations are
+ *     released.  acr_last_error() gives a thread-local message.
+ */
+#ifndef ACR_H
+#define ACR_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACR_OK = 0,
+    ACR_E_INVALID = 1,   /* bad argument (null pointer, size, eps <= 0, ...) */
+    ACR_E_NUMERIC = 2,   /* NaN/Inf or non-positive kappa detected */
+    ACR_E_NOMEM = 3,     /* device allocation failed */
+    ACR_E_SINGULAR = 4,  /* exactly singular dense leaf during H-inversion */
+    ACR_E_BREAKDOWN = 5, /* Krylov breakdown (e.g. p'Ap <= 0 in CG) */
+    ACR_E_NOTCONV = 6,   /* Krylov did not reach rtol within maxit */
+    ACR_E_DEVICE = 7,    /* HIP runtime error or no usable gfx950 device */
+    ACR_E_RANK = 8       /* rank capacity exhausted after all retries */
+} acr_status;
+
+typedef enum {
+    ACR_POISSON_HARMONIC = 0, /* -div(kappa grad u), harmonic face averages (Sec. 6) */
+    ACR_CONVDIFF_UPWIND = 1,  /* -div(kappa grad u) + beta.grad u, first-order upwind (Sec. 7) */
+    ACR_HELMHOLTZ = 2,        /* -Lap u - (omega/c)^2 u, 7-point (Sec. 8, FD variant) */
+    ACR_STENCIL7_RAW = 3      /* caller-provided 7-point stencil */
+} acr_kind;
+
+typedef enum {
+    ACR_FP64 = 0,       /* factors stored and multiplied in FP64 */
+    ACR_MIXED_FP32 = 1  /* factors stored and multiplied in FP32; leaf
+                           inversion, Gram matrices, core eigen/SVD and
+                           Krylov in FP64 */
+} acr_precision;
+
+typedef enum { ACR_CG = 0, ACR_FCG = 1, ACR_GMRES = 2 } acr_method;
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t kind;              /* acr_kind */
+    const double* kappa;       /* device, node grid; POISSON/CONVDIFF; NULL -> kappa = 1 */
+    double beta_amp;           /* CONVDIFF: beta_d(x) = beta_amp (1 + 0.5 sin(2 pi x + beta_phase)), d = x,y,z */
+    double beta_phase;
+    const double* c;           /* device, node grid; HELMHOLTZ wave speed */
+    double omega;              /* HELMHOLTZ angular frequency */
+    const double* stencil7;    /* device, 7*N; RAW: rows centre, x-1, x+1, y-1, y+1, z-1, z+1 */
+} acr_problem;
+
+typedef void* (*acr_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*acr_free_fn)(void* ptr, void* ctx);
+
+typedef struct {
+    double eps;                /* block-wise relative truncation accuracy, > 0 */
+    double eta;                /* admissibility parameter, > 0 */
+    int32_t leaf_size;         /* n_min: cluster leaves have <= leaf_size points (8..64) */
+    int32_t precision;         /* acr_precision */
+    int32_t max_rank;          /* initial rank capacity of low-rank blocks; 0 = automatic */
+    int32_t dense_work;        /* admissible blocks with min dimension <= dense_work are kept
+                                  dense (exact) during setup; 0 = paper's format everywhere */
+    acr_alloc_fn alloc;        /* optional device allocator (NULL -> hipMalloc) */
+    acr_free_fn free;
+    void* alloc_ctx;
+    uint64_t flags;            /* reserved, must be 0 */
+} acr_options;
+
+typedef struct {
+    int32_t iters;
+    double relres_true;        /* ||b - A x||_2 / ||b||_2 recomputed at exit */
+    int32_t status;            /* acr_status of the solve */
+    int32_t variant;           /* method actually used (CG may switch to FCG) */
+} acr_solve_info;
+
+#define ACR_MAX_LEVELS 32
+
+typedef struct {
+    int32_t levels;                        /* CR levels (eliminations incl. top) */
+    int32_t nplanes;                       /* nz */
+    int32_t plane_points;                  /* nx*ny */
+    int32_t clusters, dense_leaves, lr_leaves;
+    int32_t factors;                       /* stored H-matrices */
+    int32_t retries;                       /* setups redone after rank overflow */
+    int32_t rank_overflow;                 /* 1 if a rank was clamped to the capacity limit */
+    int32_t max_rank[ACR_MAX_LEVELS];      /* per CR level */
+    double mean_rank[ACR_MAX_LEVELS];
+    int32_t max_rank_all;
+    double bytes_factors;                  /* stored factor bytes (actual ranks) */
+    double bytes_allocated;                /* device bytes held by the handle */
+    double bytes_per_apply;                /* algorithmic bytes streamed by one acr_apply */
+    double setup_seconds;
+    double setup_flops;                    /* algorithmic flops counted in setup */
+    int32_t precision;
+} acr_stats_t;
+
+typedef struct acr_handle acr_handle;
+
+/* Build the ACR factorisation of the problem (Sec. 4.1-4.2).  Blocks the
+ * host until the factors are complete.  *out receives a new handle. */
+acr_status acr_setup(const acr_problem* p, const acr_options* o, void* stream,
+                     acr_handle** out);
+
+/* z = M^{-1} r, forward elimination / top solve / back substitution
+ * (Sec. 4.1) with H-matrix-vector products (Sec. 5.3).  r, z: device,
+ * N*nrhs doubles, natural ordering, column-major by right-hand side; z
+ * must not alias r. */
+acr_status acr_apply(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
+
+/* z = M^{-T} r, the exact transpose of the linear map of acr_apply. */
+acr_status acr_apply_T(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
+
+/* y = A x (transpose = 0) or A^T x (transpose = 1) with the assembled
+ * 7-point operator; x, y device, N doubles. */
+acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double* y, void* stream);
+
+/* Copy the assembled stencil (7*N doubles, layout of acr_problem.stencil7)
+ * to the device buffer out. */
+acr_status acr_get_stencil(acr_handle* h, double* out, void* stream);
+
+/* Preconditioned Krylov solve of A x = b (or A^T x = b when transpose=1,
+ * then preconditioned by acr_apply_T) from the initial guess in x,
+ * stopping at ||b - A x||/||b|| <= rtol (Sec. 5.3: CG, 2-norm, 1e-8;
+ * Sec. 7-8: GMRES).  CG: Fletcher-Reeves; FCG: Polak-Ribiere; CG switches
+ * to FCG if the residual stagnates for 5 iterations.  GMRES: right
+ * preconditioning, restart m = restart, classical Gram-Schmidt with
+ * reorthogonalisation.  Dots and norms in FP64.  Blocks the host. */
+acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t transpose,
+                        double rtol, int32_t maxit, const double* b, double* x,
+                        acr_solve_info* info, void* stream);
+
+/* Adjoint gradient for ACR_POISSON_HARMONIC: dkappa = -lam^T (dA/dkappa) u
+ * on the node grid ((nz+2)(ny+2)(nx+2) doubles, overwritten). */
+acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa,
+                          void* stream);
+
+/* Statistics of a handle (ranks, bytes, flops, timings). */
+acr_status acr_stats(const acr_handle* h, acr_stats_t* st);
+
+/* Release a handle and all device memory it owns (NULL is ignored). */
+void acr_destroy(acr_handle* h);
+
+const char* acr_status_string(acr_status s);
+const char* acr_last_error(void);
+
+/* Default options: eps 1e-4, eta 2, leaf 32, FP64, automatic capacity,
+ * dense_work 0. */
+void acr_default_options(acr_options* o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACR_H */

@@ -1,0 +1,296 @@
+"""MI355X (gfx950) accelerated cyclic reduction: thin Python binding.
+
+Argument marshalling only: every step of setup, apply, Krylov and
+gradient runs in ``libacr.so`` (HIP kernels behind the C ABI declared in
+``include/acr.h``).  PyTorch provides device memory and streams.
+
+Entry points mirror the C ABI: :func:`acr_setup`, :func:`acr_apply`,
+:func:`acr_apply_T`, :func:`acr_matvec`, :func:`krylov_solve`,
+:func:`acr_grad_kappa`, :func:`acr_stats`, :func:`acr_destroy`; plus the
+convenience wrappers :class:`Preconditioner` and :class:`ACRSolve` (a
+``torch.autograd.Function`` whose backward solves the adjoint system with
+the transposed factors).
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libacr.so")
+
+POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW = 0, 1, 2, 3
+FP64, MIXED_FP32 = 0, 1
+CG, FCG, GMRES = 0, 1, 2
+MAX_LEVELS = 32
+STATUS = ["OK", "E_INVALID", "E_NUMERIC", "E_NOMEM", "E_SINGULAR", "E_BREAKDOWN", "E_NOTCONV", "E_DEVICE",
+          "E_RANK"]
+
+
+class AcrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS[status] if 0 <= status < len(STATUS) else status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("kappa", ctypes.c_void_p), ("beta_amp", ctypes.c_double), ("beta_phase", ctypes.c_double),
+                ("c", ctypes.c_void_p), ("omega", ctypes.c_double), ("stencil7", ctypes.c_void_p)]
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("eta", ctypes.c_double), ("leaf_size", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_rank", ctypes.c_int32), ("dense_work", ctypes.c_int32),
+                ("alloc", _ALLOC), ("free", _FREE), ("alloc_ctx", ctypes.c_void_p), ("flags", ctypes.c_uint64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("relres_true", ctypes.c_double), ("status", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("nplanes", ctypes.c_int32), ("plane_points", ctypes.c_int32),
+                ("clusters", ctypes.c_int32), ("dense_leaves", ctypes.c_int32), ("lr_leaves", ctypes.c_int32),
+                ("factors", ctypes.c_int32), ("retries", ctypes.c_int32), ("rank_overflow", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32 * MAX_LEVELS), ("mean_rank", ctypes.c_double * MAX_LEVELS),
+                ("max_rank_all", ctypes.c_int32), ("bytes_factors", ctypes.c_double),
+                ("bytes_allocated", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("setup_flops", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+    def as_dict(self):
+        lv = self.levels
+        return {"levels": lv, "nplanes": self.nplanes, "plane_points": self.plane_points,
+                "clusters": self.clusters, "dense_leaves": self.dense_leaves, "lr_leaves": self.lr_leaves,
+                "factors": self.factors, "retries": self.retries, "rank_overflow": self.rank_overflow,
+                "max_rank": list(self.max_rank[:lv]), "mean_rank": list(self.mean_rank[:lv]),
+                "max_rank_all": self.max_rank_all, "bytes_factors": self.bytes_factors,
+                "bytes_allocated": self.bytes_allocated, "bytes_per_apply": self.bytes_per_apply,
+                "setup_seconds": self.setup_seconds, "precision": self.precision}
+
+
+SYMBOLS = ["acr_setup", "acr_apply", "acr_apply_T", "acr_matvec", "acr_get_stencil", "krylov_solve",
+           "acr_grad_kappa", "acr_stats", "acr_destroy", "acr_status_string", "acr_last_error",
+           "acr_default_options"]
+
+_lib = None
+
+
+def lib():
+    """Load ``libacr.so``; raises if the HIP extension has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1712_08872_amd.build`")
+    # torch ships its own HIP runtime (soname libamdhip64.so.7); loading it
+    # first makes libacr bind to that same runtime instead of a second copy
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.acr_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    L.acr_apply.argtypes = [vp, vp, vp, i32, vp]
+    L.acr_apply_T.argtypes = [vp, vp, vp, i32, vp]
+    L.acr_matvec.argtypes = [vp, i32, vp, vp, vp]
+    L.acr_get_stencil.argtypes = [vp, vp, vp]
+    L.krylov_solve.argtypes = [vp, i32, i32, i32, dbl, i32, vp, vp, ctypes.POINTER(SolveInfo), vp]
+    L.acr_grad_kappa.argtypes = [vp, vp, vp, vp, vp]
+    L.acr_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.acr_destroy.argtypes = [vp]
+    L.acr_destroy.restype = None
+    L.acr_status_string.argtypes = [i32]
+    L.acr_status_string.restype = ctypes.c_char_p
+    L.acr_last_error.restype = ctypes.c_char_p
+    L.acr_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.acr_default_options.restype = None
+    for name in ["acr_setup", "acr_apply", "acr_apply_T", "acr_matvec", "acr_get_stencil", "krylov_solve",
+                 "acr_grad_kappa", "acr_stats"]:
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise AcrError(st, lib().acr_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
+        "expected a contiguous float64 CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_options(**kw):
+    o = Options()
+    lib().acr_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """Owns an ``acr_handle``; keeps the input tensors alive."""
+
+    def __init__(self, ptr, n, keep):
+        self.ptr = ptr
+        self.n = n
+        self._keep = keep
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().acr_destroy(self.ptr)
+            self.ptr = None
+
+
+def acr_setup(nx, ny, nz, kind=POISSON_HARMONIC, kappa=None, beta_amp=0.0, beta_phase=0.0, c=None, omega=0.0,
+              stencil7=None, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64, max_rank=0, dense_work=0,
+              stream=None):
+    """``acr_setup``: returns a :class:`Handle`.  Tensors are float64 CUDA."""
+    p = Problem(nx, ny, nz, kind, _ptr(kappa), beta_amp, beta_phase, _ptr(c), omega, _ptr(stencil7))
+    o = default_options(eps=eps, eta=eta, leaf_size=leaf_size, precision=precision, max_rank=max_rank,
+                        dense_work=dense_work)
+    out = ctypes.c_void_p()
+    _check(lib().acr_setup(ctypes.byref(p), ctypes.byref(o), _stream(stream), ctypes.byref(out)))
+    return Handle(out, (nx, ny, nz), (kappa, c, stencil7))
+
+
+def acr_apply(h, r, z=None, stream=None):
+    import torch
+    z = torch.empty_like(r) if z is None else z
+    nrhs = r.numel() // (h.n[0] * h.n[1] * h.n[2])
+    _check(lib().acr_apply(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
+    return z
+
+
+def acr_apply_T(h, r, z=None, stream=None):
+    import torch
+    z = torch.empty_like(r) if z is None else z
+    nrhs = r.numel() // (h.n[0] * h.n[1] * h.n[2])
+    _check(lib().acr_apply_T(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
+    return z
+
+
+def acr_matvec(h, x, transpose=False, y=None, stream=None):
+    import torch
+    y = torch.empty_like(x) if y is None else y
+    _check(lib().acr_matvec(h.ptr, int(transpose), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+def acr_get_stencil(h, stream=None):
+    import torch
+    N = h.n[0] * h.n[1] * h.n[2]
+    out = torch.empty(7 * N, dtype=torch.float64, device="cuda")
+    _check(lib().acr_get_stencil(h.ptr, _ptr(out), _stream(stream)))
+    return out
+
+
+def krylov_solve(h, b, x=None, method=CG, restart=30, transpose=False, rtol=1e-8, maxit=1000, stream=None,
+                 raise_on_fail=True):
+    """Returns ``(x, info_dict)``."""
+    import torch
+    x = torch.zeros_like(b) if x is None else x
+    info = SolveInfo()
+    st = lib().krylov_solve(h.ptr, method, restart, int(transpose), rtol, maxit, _ptr(b), _ptr(x),
+                            ctypes.byref(info), _stream(stream))
+    d = {"iters": info.iters, "relres_true": info.relres_true, "status": info.status, "variant": info.variant}
+    if st != 0 and raise_on_fail:
+        _check(st)
+    d["status"] = st
+    return x, d
+
+
+def acr_grad_kappa(h, u, lam, out=None, stream=None):
+    import torch
+    nx, ny, nz = h.n
+    out = torch.empty((nz + 2) * (ny + 2) * (nx + 2), dtype=torch.float64, device="cuda") if out is None else out
+    _check(lib().acr_grad_kappa(h.ptr, _ptr(u), _ptr(lam), _ptr(out), _stream(stream)))
+    return out
+
+
+def acr_stats(h):
+    s = Stats()
+    _check(lib().acr_stats(h.ptr, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def acr_destroy(h):
+    h.close()
+
+
+class Preconditioner:
+    """ACR preconditioner of one problem (wraps a handle)."""
+
+    def __init__(self, nx, ny, nz, **kw):
+        self.h = acr_setup(nx, ny, nz, **kw)
+
+    def apply(self, r):
+        return acr_apply(self.h, r)
+
+    def apply_T(self, r):
+        return acr_apply_T(self.h, r)
+
+    def solve(self, b, **kw):
+        return krylov_solve(self.h, b, **kw)
+
+    def stats(self):
+        return acr_stats(self.h)
+
+
+def _make_autograd():
+    import torch
+
+    class ACRSolve(torch.autograd.Function):
+        """``u = A(kappa)^{-1} f`` for the harmonic-average Poisson operator.
+
+        forward: ACR setup + preconditioned CG.  backward: the adjoint
+        ``A^T lam = grad_u`` solved with CG preconditioned by the transposed
+        factors (``acr_apply_T``), then ``dJ/dkappa = -lam^T (dA/dkappa) u``
+        by the gradient stencil kernel; ``dJ/df = lam``.
+        """
+
+        @staticmethod
+        def forward(ctx, kappa, f, n, eps=1e-4, eta=2.0, precision=FP64, rtol=1e-10, maxit=500):
+            nx, ny, nz = n
+            kap = kappa.detach().contiguous()
+            h = acr_setup(nx, ny, nz, POISSON_HARMONIC, kappa=kap, eps=eps, eta=eta, precision=precision)
+            u, info = krylov_solve(h, f.detach().contiguous(), method=CG, rtol=rtol, maxit=maxit)
+            ctx.h = h
+            ctx.rtol, ctx.maxit = rtol, maxit
+            ctx.save_for_backward(u)
+            ctx.info = info
+            return u
+
+        @staticmethod
+        def backward(ctx, gu):
+            (u,) = ctx.saved_tensors
+            lam, _ = krylov_solve(ctx.h, gu.contiguous(), method=CG, transpose=True, rtol=ctx.rtol,
+                                  maxit=ctx.maxit)
+            gk = acr_grad_kappa(ctx.h, u, lam)
+            return gk, lam, None, None, None, None, None, None
+
+    return ACRSolve
+
+
+def __getattr__(name):
+    if name == "ACRSolve":
+        cls = _make_autograd()
+        globals()["ACRSolve"] = cls
+        return cls
+    raise AttributeError(name)

@@ -1,0 +1,114 @@
+// Device-visible records that describe one batched H-arithmetic step.
+//
+// A formatted H-product C <- beta C + alpha A B (Hackbusch's recursion on the
+// common block tree, Sec. 3-4 of the paper) is expanded once per plane
+// shape, on the host, into a list of *targets* (the leaves of C that the
+// step writes) and, per target, a list of *pieces*: the contributions of
+// the recursion that land on that leaf, each a product of stored leaves
+// restricted to a window of the target.  A kernel launch then processes
+// (batch item x target) pairs; a batch item maps the abstract roles used
+// in the pieces (e.g. "the matrix being inverted", "its scratch") to
+// concrete H-matrix instances, which is how all planes of a cyclic
+// reduction level share one launch.
+#pragma once
+#include <cstdint>
+
+namespace acr {
+
+constexpr int KC = 64;         // max columns of a low-rank accumulation round
+constexpr int TPB = 256;       // threads per block of the H-arithmetic kernels
+
+enum PieceKind : int32_t {
+  PK_LRX = 0,   // x low-rank A-leaf times a B-region (list): rank k_x
+  PK_LRY = 1,   // A-region (list) times y low-rank B-leaf: rank k_y
+  PK_DD = 2,    // dense A-leaf times dense B-leaf
+  PK_COPY = 3,  // diag(rho) * (same leaf of another instance) * diag(gamma)
+};
+
+struct DLeaf {           // device copy of the leaf table
+  int32_t m, n, r0, c0;
+  int32_t fmt, cap;
+  int64_t off;
+};
+
+struct Piece {
+  int32_t kind;
+  int32_t xrole, xleaf;  // LRX: low-rank A-leaf; DD: dense A-leaf; LRY: role of the A-list; COPY: source role/leaf
+  int32_t yrole, yleaf;  // LRY: low-rank B-leaf; DD: dense B-leaf; LRX: role of the B-list
+  int32_t l0, l1;        // list range into `lists` (leaf ids)
+  int32_t wr0, wr1;      // window rows   (H-order plane indices)
+  int32_t wc0, wc1;      // window columns
+  int32_t rv, cv;        // COPY: vector roles for row / column scaling (-1 = none)
+  double alpha;
+};
+
+struct Target {
+  int32_t crole, cleaf;
+  int32_t beta;          // 0: overwrite, 1: accumulate into the current value
+  int32_t p0, p1;        // piece range
+  int32_t direct;        // 1: beta = 0 and a single COPY piece -> exact copy
+};
+
+// flags written by kernels (device int array)
+enum Flag : int32_t {
+  FL_RANK_OVERFLOW = 0,  // a truncated rank exceeded the block's capacity
+  FL_SINGULAR = 1,       // zero pivot in a dense leaf inverse
+  FL_NONFINITE = 2,      // NaN/Inf met in a truncation
+  FL_MAXRANK = 3,        // largest rank produced (atomicMax)
+  FL_COUNT = 4
+};
+
+template <typename T>
+struct AccumArgs {
+  const DLeaf* leaves;
+  const Piece* pieces;
+  const Target* targets;
+  const int32_t* lists;
+  int32_t t0, nt;              // target range of this launch
+  int32_t nbatch, nroles, nvroles;
+  const int32_t* role_inst;    // [nbatch * nroles] instance ids (-1 = absent)
+  const double* const* vec_ptr;  // [nbatch * nvroles] H-order plane vectors
+  T* const* inst_base;         // [ninst]
+  int32_t* const* inst_rank;   // [ninst] rank arrays (one entry per leaf)
+  T* scratch;                  // per block slot: (max_m + max_n) * KC
+  int64_t scratch_stride;
+  double eps;
+  int32_t* flags;
+};
+
+struct MvTerm {
+  int32_t inst;        // H-matrix instance (-1: none or diagonal)
+  int32_t trans;
+  double alpha;
+  const double* x;     // H-order plane vector
+  const double* dvec;  // diagonal term (if inst < 0 and dvec != null)
+};
+
+struct MvJob {
+  double* y;
+  const double* base;  // optional
+  MvTerm t[2];
+};
+
+template <typename T>
+struct MvArgs {
+  const DLeaf* leaves;
+  const int32_t* lr_leaves;   // ids of low-rank leaves
+  const int64_t* soff;        // per leaf: offset of its coefficient slot (sum of caps)
+  int32_t nlr;
+  int64_t sstride;            // per (job, term) coefficient stride
+  const MvJob* jobs;
+  int32_t njobs;
+  T* const* inst_base;
+  int32_t* const* inst_rank;
+  double* coef;               // [njobs * 2 * sstride]
+  // segment -> leaves covering it (rows for N, columns for T)
+  const int32_t* seg_lo;      // [nseg + 1] H-order bounds of leaf clusters
+  const int32_t* rows_ptr;
+  const int32_t* rows_idx;
+  const int32_t* cols_ptr;
+  const int32_t* cols_idx;
+  int32_t nseg;
+};
+
+}  // namespace acr

@@ -1,0 +1,818 @@
+// H-arithmetic kernels for gfx950: batched accumulation of formatted
+// products into H-matrix leaves with truncation, dense leaf inversion and
+// the level-0 conversion of the plane operators.
+//
+// Truncation T_eps (Sec. 3.1.5, Sec. 4.3 of the paper: block-wise relative
+// accuracy, singular values sigma_i > eps sigma_1 kept): for a block given
+// as U V^T with K columns (the block's current factors concatenated with
+// the incoming contributions), the columns are norm-balanced, the Gram
+// matrices G_U = U^T U and G_V = V^T V are formed in FP64, G_V = Q L Q^T by
+// cyclic Jacobi, M = (Q L^1/2)^T G_U (Q L^1/2) = W S^2 W^T by cyclic Jacobi,
+// and U' = U Q L^1/2 W_k, V' = V Q L^-1/2 W_k.  This is the truncated SVD of
+// U V^T expressed through K x K eigenproblems; it resolves singular values
+// down to about 1e-8 sigma_1 (square root of FP64 round-off).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hprog.h"
+
+namespace acr {
+
+// ------------------------------------------------------------ utilities
+template <typename T>
+__device__ __forceinline__ int inst_of(const AccumArgs<T>& A, int b, int role) {
+  return role < 0 ? -1 : A.role_inst[b * A.nroles + role];
+}
+
+template <typename T>
+__device__ __forceinline__ T* leaf_base(const AccumArgs<T>& A, int inst, int leaf) {
+  return A.inst_base[inst] + A.leaves[leaf].off;
+}
+
+template <typename T>
+__device__ __forceinline__ int rank_of(const AccumArgs<T>& A, int inst, int leaf) {
+  return A.inst_rank[inst][leaf];
+}
+
+__device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Round-robin (tournament) pairing of K' = K + (K odd) indices: round r,
+// pair i.  Every unordered pair appears exactly once in K'-1 rounds.
+__device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
+  int M = Kp - 1;
+  p = (i == 0) ? 0 : ((i - 1 + r) % M) + 1;
+  q = ((Kp - 2 - i + r) % M) + 1;
+}
+
+// Cyclic (parallel-ordered) two-sided Jacobi for a symmetric K x K matrix
+// in LDS (leading dimension KC).  On exit A is (numerically) diagonal and
+// Q holds the eigenvectors (Q must be initialised by the caller).
+__device__ void jacobi_eig(double* A, double* Q, int K, double* cs, int* sflag) {
+  const int tid = threadIdx.x;
+  const int Kp = K + (K & 1);
+  const int np = Kp / 2;
+  if (K <= 1) return;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < Kp - 1; ++r) {
+      if (tid < np) {
+        int p, q;
+        rr_pair(Kp, r, tid, p, q);
+        double c = 1.0, s = 0.0;
+        if (p < K && q < K) {
+          if (p > q) { int t = p; p = q; q = t; }
+          double apq = A[p * KC + q];
+          double app = A[p * KC + p], aqq = A[q * KC + q];
+          if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
+            double tau = (aqq - app) / (2.0 * apq);
+            double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            *sflag = 1;
+          }
+        } else {
+          p = q = -1;
+        }
+        cs[4 * tid + 0] = c;
+        cs[4 * tid + 1] = s;
+        cs[4 * tid + 2] = (double)p;
+        cs[4 * tid + 3] = (double)q;
+      }
+      __syncthreads();
+      // rows p, q  <-  J^T A
+      for (int idx = tid; idx < np * K; idx += blockDim.x) {
+        int pi = idx / K, j = idx - pi * K;
+        int p = (int)cs[4 * pi + 2], q = (int)cs[4 * pi + 3];
+        double s = cs[4 * pi + 1];
+        if (p < 0 || s == 0.0) continue;
+        double c = cs[4 * pi];
+        double ap = A[p * KC + j], aq = A[q * KC + j];
+        A[p * KC + j] = c * ap - s * aq;
+        A[q * KC + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q  <-  A J ;  Q <- Q J
+      for (int idx = tid; idx < np * K; idx += blockDim.x) {
+        int pi = idx / K, i = idx - pi * K;
+        int p = (int)cs[4 * pi + 2], q = (int)cs[4 * pi + 3];
+        double s = cs[4 * pi + 1];
+        if (p < 0 || s == 0.0) continue;
+        double c = cs[4 * pi];
+        double ap = A[i * KC + p], aq = A[i * KC + q];
+        A[i * KC + p] = c * ap - s * aq;
+        A[i * KC + q] = s * ap + c * aq;
+        double qp = Q[i * KC + p], qq = Q[i * KC + q];
+        Q[i * KC + p] = c * qp - s * qq;
+        Q[i * KC + q] = s * qp + c * qq;
+      }
+      __syncthreads();
+    }
+    int f = *sflag;
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
+struct Lds {
+  double S0[KC * KC];
+  double S1[KC * KC];
+  double S2[KC * KC];
+  double S3[KC * KC];
+  double v0[KC], v1[KC], v2[KC], v3[KC];
+  double cs[4 * (KC / 2 + 1)];
+  int keep[KC], order[KC];
+  int ival[8];
+};
+
+// Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
+// matrix with `rows` rows, accumulated in FP64 into G (ld KC).  `tile` is
+// an LDS staging buffer of KC x KC doubles.
+template <typename T>
+__device__ void gram(const T* X, int rows, int K, double* G, double* tile) {
+  const int tid = threadIdx.x;
+  constexpr int PER = KC * KC / TPB;
+  double acc[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) acc[e] = 0.0;
+  for (int r0 = 0; r0 < rows; r0 += KC) {
+    int nr = imin(KC, rows - r0);
+    for (int idx = tid; idx < KC * KC; idx += TPB) {
+      int rr = idx / KC, j = idx - rr * KC;
+      tile[idx] = (rr < nr && j < K) ? (double)X[(int64_t)(r0 + rr) * KC + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      int idx = tid + e * TPB;
+      int i = idx / KC, j = idx - i * KC;
+      if (i < K && j < K) {
+        double s = 0.0;
+        for (int rr = 0; rr < nr; ++rr) s += tile[rr * KC + i] * tile[rr * KC + j];
+        acc[e] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    int idx = tid + e * TPB;
+    int i = idx / KC, j = idx - i * KC;
+    if (i < K && j < K) G[i * KC + j] = acc[e];
+  }
+  __syncthreads();
+}
+
+// In place X[:, 0:k] = X[:, 0:K] R (row-major ld KC, R is K x k in LDS ld KC).
+template <typename T>
+__device__ void rebuild(T* X, int rows, int K, int k, const double* R, double* tile) {
+  const int tid = threadIdx.x;
+  for (int r0 = 0; r0 < rows; r0 += KC) {
+    int nr = imin(KC, rows - r0);
+    for (int idx = tid; idx < KC * KC; idx += TPB) {
+      int rr = idx / KC, j = idx - rr * KC;
+      tile[idx] = (rr < nr && j < K) ? (double)X[(int64_t)(r0 + rr) * KC + j] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nr * k; idx += TPB) {
+      int rr = idx / k, c = idx - rr * k;
+      double s = 0.0;
+      for (int i = 0; i < K; ++i) s += tile[rr * KC + i] * R[i * KC + c];
+      X[(int64_t)(r0 + rr) * KC + c] = (T)s;
+    }
+    __syncthreads();
+  }
+}
+
+// T_eps of Us Vs^T (m x K and n x K row-major scratch); on exit the first k
+// columns hold the truncated factors (singular values folded into U).
+// Returns k.
+template <typename T>
+__device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds& L, int32_t* flags) {
+  const int tid = threadIdx.x;
+  if (K == 0) return 0;
+  gram(Us, m, K, L.S2, L.S1);
+  gram(Vs, n, K, L.S0, L.S1);
+  // norm balancing of the column pairs: d_j = sqrt(|v_j| / |u_j|)
+  if (tid < K) {
+    double nu = L.S2[tid * KC + tid], nv = L.S0[tid * KC + tid];
+    double d = (nu > 0.0 && nv > 0.0 && isfinite(nu) && isfinite(nv)) ? sqrt(sqrt(nv / nu)) : 0.0;
+    L.v0[tid] = d;
+    if (!isfinite(nu) || !isfinite(nv)) atomicOr(&flags[FL_NONFINITE], 1);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < K * K; idx += TPB) {
+    int i = idx / K, j = idx - i * K;
+    double di = L.v0[i], dj = L.v0[j];
+    L.S2[i * KC + j] *= di * dj;
+    L.S0[i * KC + j] = (di > 0.0 && dj > 0.0) ? L.S0[i * KC + j] / (di * dj) : 0.0;
+    L.S1[i * KC + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_eig(L.S0, L.S1, K, L.cs, &L.ival[0]);
+  // eigenvalues of G_V; keep the numerically non-zero ones
+  if (tid == 0) {
+    double lmax = 0.0;
+    for (int i = 0; i < K; ++i) lmax = fmax(lmax, L.S0[i * KC + i]);
+    int kp = 0;
+    for (int i = 0; i < K; ++i)
+      if (lmax > 0.0 && L.S0[i * KC + i] > 1e-15 * lmax) L.keep[kp++] = i;
+    L.ival[1] = kp;
+  }
+  __syncthreads();
+  const int Kp = L.ival[1];
+  if (Kp == 0) return 0;
+  // L = Q_keep diag(sqrt(lambda)) -> S3 (K x Kp); v1 = lambda_keep
+  for (int idx = tid; idx < K * Kp; idx += TPB) {
+    int i = idx / Kp, a = idx - i * Kp;
+    int ka = L.keep[a];
+    double lam = L.S0[ka * KC + ka];
+    L.S3[i * KC + a] = L.S1[i * KC + ka] * sqrt(lam);
+    if (i == 0) L.v1[a] = lam;
+  }
+  __syncthreads();
+  // temp = G_U L -> S1
+  for (int idx = tid; idx < K * Kp; idx += TPB) {
+    int i = idx / Kp, a = idx - i * Kp;
+    double s = 0.0;
+    for (int j = 0; j < K; ++j) s += L.S2[i * KC + j] * L.S3[j * KC + a];
+    L.S1[i * KC + a] = s;
+  }
+  __syncthreads();
+  // M = L^T temp -> S0 (Kp x Kp, symmetrised)
+  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
+    int a = idx / Kp, c = idx - a * Kp;
+    double s = 0.0;
+    for (int i = 0; i < K; ++i) s += L.S3[i * KC + a] * L.S1[i * KC + c];
+    L.S0[a * KC + c] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
+    int a = idx / Kp, c = idx - a * Kp;
+    if (a < c) {
+      double s = 0.5 * (L.S0[a * KC + c] + L.S0[c * KC + a]);
+      L.S0[a * KC + c] = s;
+      L.S0[c * KC + a] = s;
+    }
+  }
+  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
+    int a = idx / Kp, c = idx - a * Kp;
+    L.S1[a * KC + c] = (a == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_eig(L.S0, L.S1, Kp, L.cs, &L.ival[0]);
+  // singular values, descending order, truncation rank
+  if (tid < Kp) L.v2[tid] = sqrt(fmax(L.S0[tid * KC + tid], 0.0));
+  __syncthreads();
+  if (tid < Kp) {
+    double sa = L.v2[tid];
+    int rnk = 0;
+    for (int b = 0; b < Kp; ++b) {
+      double sb = L.v2[b];
+      if (sb > sa || (sb == sa && b < tid)) ++rnk;
+    }
+    L.order[rnk] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s1 = L.v2[L.order[0]];
+    int k = 0;
+    if (s1 > 0.0 && isfinite(s1))
+      while (k < Kp && L.v2[L.order[k]] > eps * s1) ++k;
+    if (!isfinite(s1)) atomicOr(&flags[FL_NONFINITE], 1);
+    L.ival[2] = k;
+  }
+  __syncthreads();
+  const int k = L.ival[2];
+  if (k == 0) return 0;
+  // R_U = diag(d) L W_k -> S2 ;  R_V = diag(1/d) L diag(1/lambda) W_k -> S0
+  // (S0 is overwritten column by column after W is read from S1; the
+  //  eigenvalues are already in v2)
+  for (int idx = tid; idx < K * k; idx += TPB) {
+    int i = idx / k, c = idx - i * k;
+    int w = L.order[c];
+    double su = 0.0, sv = 0.0;
+    for (int a = 0; a < Kp; ++a) {
+      double la = L.S3[i * KC + a] * L.S1[a * KC + w];
+      su += la;
+      sv += la / L.v1[a];
+    }
+    double d = L.v0[i];
+    L.S2[i * KC + c] = su * d;
+    L.S0[i * KC + c] = (d > 0.0) ? sv / d : 0.0;
+  }
+  __syncthreads();
+  rebuild(Us, m, K, k, L.S2, L.S1);
+  rebuild(Vs, n, K, k, L.S0, L.S1);
+  return k;
+}
+
+// ------------------------------------------------------------ pieces
+// Number of columns a piece contributes to a low-rank target.
+template <typename T>
+__device__ int piece_width(const AccumArgs<T>& A, int b, const Piece& P) {
+  switch (P.kind) {
+    case PK_LRX: {
+      int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+      return (xi < 0 || yi < 0) ? 0 : rank_of(A, xi, P.xleaf);
+    }
+    case PK_LRY: {
+      int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+      return (xi < 0 || yi < 0) ? 0 : rank_of(A, yi, P.yleaf);
+    }
+    case PK_DD: {
+      int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+      return (xi < 0 || yi < 0) ? 0 : (P.wc1 - P.wc0);
+    }
+    case PK_COPY: {
+      int si = inst_of(A, b, P.xrole);
+      if (si < 0) return 0;
+      return A.leaves[P.xleaf].fmt == 1 ? rank_of(A, si, P.xleaf) : A.leaves[P.xleaf].n;
+    }
+  }
+  return 0;
+}
+
+// Write columns [j0, j0+take) of a piece into scratch columns [K, K+take)
+// of Us (target rows) and Vs (target columns), row-major ld KC.  The alpha
+// of the piece is folded into Us.
+template <typename T>
+__device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0,
+                              int take, T* Us, T* Vs, int K, double* Z) {
+  const int tid = threadIdx.x;
+  const int m = tc.m, n = tc.n;
+  const double alpha = P.alpha;
+  if (P.kind == PK_LRX) {
+    const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+    const DLeaf x = A.leaves[P.xleaf];
+    const T* Ux = leaf_base(A, xi, P.xleaf);
+    const T* Vx = Ux + (int64_t)x.m * x.cap;
+    for (int idx = tid; idx < m * take; idx += TPB) {
+      int i = idx / take, jj = idx - i * take;
+      int gi = tc.r0 + i;
+      double v = (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * x.m] : 0.0;
+      Us[(int64_t)i * KC + K + jj] = (T)v;
+    }
+    for (int idx = tid; idx < n * take; idx += TPB) {
+      int c = idx / take, jj = idx - c * take;
+      Vs[(int64_t)c * KC + K + jj] = (T)0;
+    }
+    __syncthreads();
+    for (int li = P.l0; li < P.l1; ++li) {
+      const int l = A.lists[li];
+      const DLeaf lam = A.leaves[l];
+      const int cA = imax(lam.c0, P.wc0), cB = imin(lam.c0 + lam.n, P.wc1);
+      if (cA >= cB) continue;
+      const T* lp = leaf_base(A, yi, l);
+      // middle index range shared by lam's rows and x's columns
+      const int q0 = imax(lam.r0, x.c0), q1 = imin(lam.r0 + lam.m, x.c0 + x.n);
+      if (q0 >= q1) continue;
+      const int nq = q1 - q0;
+      if (lam.fmt == 0) {
+        for (int idx = tid; idx < (cB - cA) * take; idx += TPB) {
+          int cc = idx / take, jj = idx - cc * take;
+          int c = cA + cc;
+          const T* col = lp + (int64_t)(c - lam.c0) * lam.m + (q0 - lam.r0);
+          const T* vx = Vx + (q0 - x.c0) + (int64_t)(j0 + jj) * x.n;
+          double s = 0.0;
+          for (int r = 0; r < nq; ++r) s += (double)col[r] * (double)vx[r];
+          T* dst = &Vs[(int64_t)(c - tc.c0) * KC + K + jj];
+          *dst = (T)((double)*dst + s);
+        }
+      } else {
+        const int kl = rank_of(A, yi, l);
+        if (kl == 0) continue;
+        const T* Ul = lp;
+        const T* Vl = lp + (int64_t)lam.m * lam.cap;
+        for (int idx = tid; idx < kl * take; idx += TPB) {
+          int a = idx / take, jj = idx - a * take;
+          const T* ua = Ul + (int64_t)a * lam.m + (q0 - lam.r0);
+          const T* vx = Vx + (q0 - x.c0) + (int64_t)(j0 + jj) * x.n;
+          double s = 0.0;
+          for (int r = 0; r < nq; ++r) s += (double)ua[r] * (double)vx[r];
+          Z[a * KC + jj] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (cB - cA) * take; idx += TPB) {
+          int cc = idx / take, jj = idx - cc * take;
+          int c = cA + cc;
+          double s = 0.0;
+          for (int a = 0; a < kl; ++a) s += (double)Vl[(c - lam.c0) + (int64_t)a * lam.n] * Z[a * KC + jj];
+          T* dst = &Vs[(int64_t)(c - tc.c0) * KC + K + jj];
+          *dst = (T)((double)*dst + s);
+        }
+      }
+      __syncthreads();
+    }
+  } else if (P.kind == PK_LRY) {
+    const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+    const DLeaf y = A.leaves[P.yleaf];
+    const T* Uy = leaf_base(A, yi, P.yleaf);
+    const T* Vy = Uy + (int64_t)y.m * y.cap;
+    for (int idx = tid; idx < n * take; idx += TPB) {
+      int c = idx / take, jj = idx - c * take;
+      int gc = tc.c0 + c;
+      double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * y.n] : 0.0;
+      Vs[(int64_t)c * KC + K + jj] = (T)v;
+    }
+    for (int idx = tid; idx < m * take; idx += TPB) {
+      int i = idx / take, jj = idx - i * take;
+      Us[(int64_t)i * KC + K + jj] = (T)0;
+    }
+    __syncthreads();
+    for (int li = P.l0; li < P.l1; ++li) {
+      const int l = A.lists[li];
+      const DLeaf lam = A.leaves[l];
+      const int rA = imax(lam.r0, P.wr0), rB = imin(lam.r0 + lam.m, P.wr1);
+      if (rA >= rB) continue;
+      const T* lp = leaf_base(A, xi, l);
+      // middle index range shared by lam's columns and y's rows
+      const int q0 = imax(lam.c0, y.r0), q1 = imin(lam.c0 + lam.n, y.r0 + y.m);
+      if (q0 >= q1) continue;
+      const int nq = q1 - q0;
+      if (lam.fmt == 0) {
+        for (int idx = tid; idx < (rB - rA) * take; idx += TPB) {
+          int ii = idx / take, jj = idx - ii * take;
+          int i = rA + ii;
+          const T* uy = Uy + (q0 - y.r0) + (int64_t)(j0 + jj) * y.m;
+          const T* row = lp + (i - lam.r0) + (int64_t)(q0 - lam.c0) * lam.m;
+          double s = 0.0;
+          for (int q = 0; q < nq; ++q) s += (double)row[(int64_t)q * lam.m] * (double)uy[q];
+          T* dst = &Us[(int64_t)(i - tc.r0) * KC + K + jj];
+          *dst = (T)((double)*dst + alpha * s);
+        }
+      } else {
+        const int kl = rank_of(A, xi, l);
+        if (kl == 0) continue;
+        const T* Ul = lp;
+        const T* Vl = lp + (int64_t)lam.m * lam.cap;
+        for (int idx = tid; idx < kl * take; idx += TPB) {
+          int a = idx / take, jj = idx - a * take;
+          const T* va = Vl + (int64_t)a * lam.n + (q0 - lam.c0);
+          const T* uy = Uy + (q0 - y.r0) + (int64_t)(j0 + jj) * y.m;
+          double s = 0.0;
+          for (int q = 0; q < nq; ++q) s += (double)va[q] * (double)uy[q];
+          Z[a * KC + jj] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (rB - rA) * take; idx += TPB) {
+          int ii = idx / take, jj = idx - ii * take;
+          int i = rA + ii;
+          double s = 0.0;
+          for (int a = 0; a < kl; ++a) s += (double)Ul[(i - lam.r0) + (int64_t)a * lam.m] * Z[a * KC + jj];
+          T* dst = &Us[(int64_t)(i - tc.r0) * KC + K + jj];
+          *dst = (T)((double)*dst + alpha * s);
+        }
+      }
+      __syncthreads();
+    }
+  } else if (P.kind == PK_DD) {
+    // dense product into a low-rank target: U-part = alpha P[:, cols], V-part = selector
+    const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+    const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
+    const T* xp = leaf_base(A, xi, P.xleaf);
+    const T* yp = leaf_base(A, yi, P.yleaf);
+    const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
+    for (int idx = tid; idx < m * take; idx += TPB) {
+      int i = idx / take, jj = idx - i * take;
+      int gi = tc.r0 + i, gc = P.wc0 + j0 + jj;
+      double s = 0.0;
+      if (gi >= P.wr0 && gi < P.wr1) {
+        for (int q = M0; q < M1; ++q)
+          s += (double)xp[(gi - x.r0) + (int64_t)(q - x.c0) * x.m] * (double)yp[(q - y.r0) + (int64_t)(gc - y.c0) * y.m];
+      }
+      Us[(int64_t)i * KC + K + jj] = (T)(alpha * s);
+    }
+    for (int idx = tid; idx < n * take; idx += TPB) {
+      int c = idx / take, jj = idx - c * take;
+      Vs[(int64_t)c * KC + K + jj] = (T)((tc.c0 + c == P.wc0 + j0 + jj) ? 1.0 : 0.0);
+    }
+  } else {  // PK_COPY of a low-rank leaf
+    const int si = inst_of(A, b, P.xrole);
+    const DLeaf s = A.leaves[P.xleaf];
+    const T* Usrc = leaf_base(A, si, P.xleaf);
+    const T* Vsrc = Usrc + (int64_t)s.m * s.cap;
+    const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
+    const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
+    for (int idx = tid; idx < m * take; idx += TPB) {
+      int i = idx / take, jj = idx - i * take;
+      double v = alpha * (double)Usrc[i + (int64_t)(j0 + jj) * s.m];
+      if (rho) v *= rho[tc.r0 + i];
+      Us[(int64_t)i * KC + K + jj] = (T)v;
+    }
+    for (int idx = tid; idx < n * take; idx += TPB) {
+      int c = idx / take, jj = idx - c * take;
+      double v = (double)Vsrc[c + (int64_t)(j0 + jj) * s.n];
+      if (gam) v *= gam[tc.c0 + c];
+      Vs[(int64_t)c * KC + K + jj] = (T)v;
+    }
+  }
+  __syncthreads();
+}
+
+// Dense target: C[win] += Us Vs^T for `take` columns.
+template <typename T>
+__device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take) {
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+    int i = idx % tc.m, c = idx / tc.m;
+    double s = 0.0;
+    for (int jj = 0; jj < take; ++jj) s += (double)Us[(int64_t)i * KC + jj] * (double)Vs[(int64_t)c * KC + jj];
+    C[idx] = (T)((double)C[idx] + s);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ main kernel
+template <typename T>
+__global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
+  __shared__ Lds L;
+  const int tid = threadIdx.x;
+  const int total = A.nbatch * A.nt;
+  T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = item / A.nt;
+    const Target tg = A.targets[A.t0 + item % A.nt];
+    const int ci = inst_of(A, b, tg.crole);
+    if (ci < 0) continue;
+    const DLeaf tc = A.leaves[tg.cleaf];
+    T* C = leaf_base(A, ci, tg.cleaf);
+    T* Vs = Us + (int64_t)tc.m * KC;
+    if (tc.fmt == 0) {
+      // ---------------- dense target
+      if (!tg.beta)
+        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
+      __syncthreads();
+      for (int p = tg.p0; p < tg.p1; ++p) {
+        const Piece P = A.pieces[p];
+        if (P.kind == PK_DD) {
+          const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+          if (xi < 0 || yi < 0) continue;
+          const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
+          const T* xp = leaf_base(A, xi, P.xleaf);
+          const T* yp = leaf_base(A, yi, P.yleaf);
+          const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
+          const int wr = P.wr1 - P.wr0, wc = P.wc1 - P.wc0;
+          for (int idx = tid; idx < wr * wc; idx += TPB) {
+            int gi = P.wr0 + idx % wr, gc = P.wc0 + idx / wr;
+            double s = 0.0;
+            for (int q = M0; q < M1; ++q)
+              s += (double)xp[(gi - x.r0) + (int64_t)(q - x.c0) * x.m] * (double)yp[(q - y.r0) + (int64_t)(gc - y.c0) * y.m];
+            T* dst = &C[(gi - tc.r0) + (int64_t)(gc - tc.c0) * tc.m];
+            *dst = (T)((double)*dst + P.alpha * s);
+          }
+          __syncthreads();
+        } else if (P.kind == PK_COPY) {
+          const int si = inst_of(A, b, P.xrole);
+          if (si < 0) continue;
+          const T* src = leaf_base(A, si, P.xleaf);
+          const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
+          const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
+          for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+            int i = idx % tc.m, c = idx / tc.m;
+            double v = P.alpha * (double)src[idx];
+            if (rho) v *= rho[tc.r0 + i];
+            if (gam) v *= gam[tc.c0 + c];
+            C[idx] = (T)((double)C[idx] + v);
+          }
+          __syncthreads();
+        } else {
+          const int w = piece_width(A, b, P);
+          for (int j0 = 0; j0 < w; j0 += KC) {
+            int take = imin(KC, w - j0);
+            piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L.S0);
+            dense_add_outer(C, tc, Us, Vs, take);
+          }
+        }
+      }
+      continue;
+    }
+    // ---------------- low-rank target
+    int32_t* rk = &A.inst_rank[ci][tg.cleaf];
+    T* Uc = C;
+    T* Vc = C + (int64_t)tc.m * tc.cap;
+    if (tg.direct) {
+      const Piece P = A.pieces[tg.p0];
+      const int si = inst_of(A, b, P.xrole);
+      const int ks = si < 0 ? 0 : rank_of(A, si, P.xleaf);
+      const T* Usrc = si < 0 ? nullptr : leaf_base(A, si, P.xleaf);
+      const T* Vsrc = si < 0 ? nullptr : Usrc + (int64_t)tc.m * tc.cap;
+      const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
+      const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
+      for (int idx = tid; idx < tc.m * ks; idx += TPB) {
+        int i = idx % tc.m;
+        double v = P.alpha * (double)Usrc[idx];
+        if (rho) v *= rho[tc.r0 + i];
+        Uc[idx] = (T)v;
+      }
+      for (int idx = tid; idx < tc.n * ks; idx += TPB) {
+        int c = idx % tc.n;
+        double v = (double)Vsrc[idx];
+        if (gam) v *= gam[tc.c0 + c];
+        Vc[idx] = (T)v;
+      }
+      if (tid == 0) *rk = ks;
+      __syncthreads();
+      continue;
+    }
+    int K = 0;
+    if (tg.beta) {
+      const int k0 = *rk;
+      for (int idx = tid; idx < tc.m * k0; idx += TPB) {
+        int i = idx % tc.m, j = idx / tc.m;
+        Us[(int64_t)i * KC + j] = Uc[idx];
+      }
+      for (int idx = tid; idx < tc.n * k0; idx += TPB) {
+        int c = idx % tc.n, j = idx / tc.n;
+        Vs[(int64_t)c * KC + j] = Vc[idx];
+      }
+      K = k0;
+      __syncthreads();
+    }
+    for (int p = tg.p0; p < tg.p1; ++p) {
+      const Piece P = A.pieces[p];
+      const int w = piece_width(A, b, P);
+      int j0 = 0;
+      while (j0 < w) {
+        if (K == KC) {
+          // intermediate recompression; keep room for the next columns
+          K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags);
+          if (K > KC - 8) {
+            if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
+            K = KC - 8;
+          }
+        }
+        int take = imin(w - j0, KC - K);
+        piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L.S0);
+        K += take;
+        j0 += take;
+      }
+    }
+    if (tg.p1 > tg.p0 || !tg.beta) {
+      int k = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags);
+      int kw = imin(k, tc.cap);
+      if (tid == 0) {
+        if (k > tc.cap) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
+        atomicMax(&A.flags[FL_MAXRANK], k);
+        *rk = kw;
+      }
+      for (int idx = tid; idx < tc.m * kw; idx += TPB) {
+        int i = idx % tc.m, j = idx / tc.m;
+        Uc[idx] = Us[(int64_t)i * KC + j];
+      }
+      for (int idx = tid; idx < tc.n * kw; idx += TPB) {
+        int c = idx % tc.n, j = idx / tc.n;
+        Vc[idx] = Vs[(int64_t)c * KC + j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ leaf inverse
+// In-place inverse of dense diagonal leaves by Gauss-Jordan elimination with
+// partial pivoting in FP64 (one block per instance).
+template <typename T>
+__global__ __launch_bounds__(TPB) void leaf_inverse_kernel(T* const* inst_base, const int32_t* insts, int stride,
+                                                          int ninst, int64_t off, int m, int32_t* flags) {
+  __shared__ double W[64 * 129];
+  __shared__ double red[TPB];
+  __shared__ int redi[TPB];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x;
+  const int ld = 2 * m + 1;
+  for (int it = blockIdx.x; it < ninst; it += gridDim.x) {
+    T* a = inst_base[insts[it * stride]] + off;
+    for (int idx = tid; idx < m * 2 * m; idx += TPB) {
+      int i = idx / (2 * m), j = idx - i * 2 * m;
+      W[i * ld + j] = (j < m) ? (double)a[i + (int64_t)j * m] : (j - m == i ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < m; i += TPB) {
+        double v = fabs(W[i * ld + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+      red[tid] = best;
+      redi[tid] = bi;
+      __syncthreads();
+      for (int s = TPB / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+          if (red[tid + s] > red[tid] || (red[tid + s] == red[tid] && redi[tid + s] < redi[tid])) {
+            red[tid] = red[tid + s];
+            redi[tid] = redi[tid + s];
+          }
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        piv_s = redi[0];
+        if (!(red[0] > 0.0)) atomicOr(&flags[FL_SINGULAR], 1);
+      }
+      __syncthreads();
+      const int p = piv_s;
+      if (p != k)
+        for (int j = tid; j < 2 * m; j += TPB) {
+          double t = W[k * ld + j];
+          W[k * ld + j] = W[p * ld + j];
+          W[p * ld + j] = t;
+        }
+      __syncthreads();
+      const double pv = W[k * ld + k];
+      const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+      __syncthreads();
+      for (int j = tid; j < 2 * m; j += TPB) W[k * ld + j] *= inv;
+      __syncthreads();
+      for (int idx = tid; idx < m * 2 * m; idx += TPB) {
+        int i = idx / (2 * m), j = idx - i * 2 * m;
+        if (i == k || j == k) continue;
+        W[i * ld + j] -= W[i * ld + k] * W[k * ld + j];
+      }
+      __syncthreads();
+      for (int i = tid; i < m; i += TPB)
+        if (i != k) W[i * ld + k] = 0.0;
+      __syncthreads();
+    }
+    for (int idx = tid; idx < m * m; idx += TPB) {
+      int i = idx % m, j = idx / m;
+      a[idx] = (T)W[i * ld + m + j];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ level 0
+// D_k^(0): write the in-plane 5-point couplings of every plane into the
+// dense leaves of its H-matrix instance (the low-rank leaves start empty).
+// map[d * B + i] = element offset inside the instance of the entry
+// (row i, column of neighbour d) or -1; d = centre, x-1, x+1, y-1, y+1.
+template <typename T>
+__global__ void level0_kernel(T* const* inst_base, const int32_t* insts, int nplanes, int plane0, const double* S,
+                              int64_t N, int B, const int32_t* perm, const int64_t* map) {
+  const int64_t total = (int64_t)nplanes * B;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    int k = (int)(g / B), i = (int)(g - (int64_t)k * B);
+    int64_t p = (int64_t)(plane0 + k) * B + perm[i];
+    T* base = inst_base[insts[k]];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      int64_t o = map[(int64_t)d * B + i];
+      if (o >= 0) base[o] = (T)S[(int64_t)d * N + p];
+    }
+  }
+}
+
+// H-ordered z-couplings of every plane: out[k*B + i] = S[row][k*B + perm[i]].
+__global__ void zcoupling_kernel(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA,
+                                 double* outC) {
+  const int64_t total = (int64_t)nz * B;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+    int k = (int)(g / B), i = (int)(g - (int64_t)k * B);
+    int64_t p = (int64_t)k * B + perm[i];
+    outA[g] = S[5 * N + p];
+    outC[g] = S[6 * N + p];
+  }
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+void launch_accum(const AccumArgs<T>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(accum_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
+}
+template <typename T>
+void launch_leaf_inverse(T* const* base, const int32_t* insts, int stride, int ninst, int64_t off, int m,
+                         int32_t* flags, hipStream_t s) {
+  int grid = ninst < 1024 ? ninst : 1024;
+  hipLaunchKernelGGL(leaf_inverse_kernel<T>, dim3(grid), dim3(TPB), 0, s, base, insts, stride, ninst, off, m, flags);
+}
+template <typename T>
+void launch_level0(T* const* base, const int32_t* insts, int nplanes, int plane0, const double* S, int64_t N, int B,
+                   const int32_t* perm, const int64_t* map, hipStream_t s) {
+  int64_t total = (int64_t)nplanes * B;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 65535) grid = 65535;
+  hipLaunchKernelGGL(level0_kernel<T>, dim3(grid), dim3(256), 0, s, base, insts, nplanes, plane0, S, N, B, perm, map);
+}
+void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
+                      hipStream_t s) {
+  int64_t total = (int64_t)nz * B;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 65535) grid = 65535;
+  hipLaunchKernelGGL(zcoupling_kernel, dim3(grid), dim3(256), 0, s, S, N, B, nz, perm, outA, outC);
+}
+
+template void launch_accum<double>(const AccumArgs<double>&, int, hipStream_t);
+template void launch_accum<float>(const AccumArgs<float>&, int, hipStream_t);
+template void launch_leaf_inverse<double>(double* const*, const int32_t*, int, int, int64_t, int, int32_t*,
+                                          hipStream_t);
+template void launch_leaf_inverse<float>(float* const*, const int32_t*, int, int, int64_t, int, int32_t*, hipStream_t);
+template void launch_level0<double>(double* const*, const int32_t*, int, int, const double*, int64_t, int,
+                                    const int32_t*, const int64_t*, hipStream_t);
+template void launch_level0<float>(float* const*, const int32_t*, int, int, const double*, int64_t, int,
+                                   const int32_t*, const int64_t*, hipStream_t);
+
+}  // namespace acr

@@ -1,0 +1,174 @@
+// Handle state and internal interfaces of the ACR runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/acr.h"
+#include "geometry.h"
+#include "hprog.h"
+#include "program.h"
+
+namespace acr {
+
+struct AcrError : std::runtime_error {
+  acr_status st;
+  AcrError(acr_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHK(expr)                                                                                 \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      throw ::acr::AcrError(e_ == hipErrorOutOfMemory ? ACR_E_NOMEM : ACR_E_DEVICE,                  \
+                            std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+// kernel launchers
+template <typename T> void launch_accum(const AccumArgs<T>&, int grid, hipStream_t);
+template <typename T>
+void launch_leaf_inverse(T* const*, const int32_t*, int stride, int ninst, int64_t off, int m, int32_t* flags,
+                         hipStream_t);
+template <typename T>
+void launch_level0(T* const*, const int32_t*, int nplanes, int plane0, const double* S, int64_t N, int B,
+                   const int32_t* perm, const int64_t* map, hipStream_t);
+void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
+                      hipStream_t);
+template <typename T> void launch_mv(const MvArgs<T>&, hipStream_t);
+void launch_assemble(int kind, int nx, int ny, int nz, const double* kappa, double ba, double bph, const double* c,
+                     double omega, double* S, hipStream_t);
+void launch_stencil_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t);
+void launch_grad_kappa(int nx, int ny, int nz, const double* kappa, const double* u, const double* lam, double* g,
+                       hipStream_t);
+void launch_to_horder(const double* n, double* h, const int32_t* perm, int B, int64_t N, hipStream_t);
+void launch_from_horder(const double* h, double* n, const int32_t* perm, int B, int64_t N, hipStream_t);
+void launch_dots(const double* const* a, const double* const* b, int nd, int64_t n, double* part, double* out,
+                 hipStream_t);
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t);
+void launch_multi_dot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part, double* out,
+                      hipStream_t);
+void launch_multi_axpy(int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w, double sign,
+                       hipStream_t);
+void launch_lincomb(int64_t n, int nv, const double* V, int64_t ldv, const double* c, double beta, double* y,
+                    hipStream_t);
+void launch_check(const double* x, int64_t n, int positive, int32_t* flag, hipStream_t);
+
+// One stored or working H-matrix of a plane.
+struct Instance {
+  void* base = nullptr;      // inst_elems * sizeof(T) followed by nleaf int32 ranks
+  int32_t* rank = nullptr;
+  bool live = false;
+};
+
+struct Coupling {            // coupling of a plane to its previous (A) or next (C) plane
+  int kind = 0;              // 0 absent, 1 diagonal (level 0), 2 H-matrix instance
+  int inst = -1;
+  const double* diag = nullptr;  // H-order plane vector
+};
+
+struct Level {
+  std::vector<int> P, E, K;
+  std::map<int, int> dinv;   // eliminated plane -> instance
+  std::map<int, Coupling> A, C;
+};
+
+struct PhaseJobs {           // device job array of one apply phase
+  MvJob* d = nullptr;
+  int n = 0;
+};
+
+struct Handle {
+  // problem
+  int nx = 0, ny = 0, nz = 0, kind = 0, B = 0;
+  int64_t N = 0;
+  acr_options opt{};
+  bool fp32 = false;
+  double beta_amp = 0, beta_phase = 0, omega = 0;
+  // allocator
+  std::vector<std::pair<void*, size_t>> owned;
+  size_t bytes_alloc = 0;
+  void* dmalloc(size_t bytes);
+  void dfree(void* p);
+  template <typename X> X* dnew(size_t n) { return (X*)dmalloc(n * sizeof(X)); }
+  template <typename X> X* upload(const std::vector<X>& v) {
+    if (v.empty()) return nullptr;
+    X* p = dnew<X>(v.size());
+    HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+    return p;
+  }
+  // assembled operator and inputs kept by the handle
+  double* S = nullptr;       // 7 * N
+  double* kappa = nullptr;   // node grid copy (Poisson/convdiff)
+  // geometry and device tables
+  Geometry G;
+  DLeaf* d_leaves = nullptr;
+  int32_t* d_perm = nullptr;
+  int64_t* d_l0map = nullptr;
+  int32_t *d_seg_lo = nullptr, *d_rows_ptr = nullptr, *d_rows_idx = nullptr, *d_cols_ptr = nullptr,
+          *d_cols_idx = nullptr, *d_lr_leaves = nullptr;
+  int64_t* d_soff = nullptr;
+  int64_t sstride = 0;
+  // instances
+  std::vector<Instance> inst;
+  void** d_inst_base = nullptr;
+  int32_t** d_inst_rank = nullptr;
+  int inst_table_cap = 0;
+  bool table_dirty = true;
+  std::vector<int> free_inst;
+  int new_instance(hipStream_t s);
+  void release_instance(int id);
+  void sync_tables();
+  // programs
+  Program inv_prog;
+  std::map<std::string, Program> prog;
+  Program& get_program(const std::string& key);
+  void upload_program(Program& p);
+  // scratch for accumulation
+  void* scratch = nullptr;
+  int64_t scratch_stride = 0;
+  int scratch_slots = 0;
+  int32_t* d_flags = nullptr;
+  int32_t* d_roles = nullptr;
+  int roles_cap = 0;
+  const double** d_vecs = nullptr;
+  int vecs_cap = 0;
+  // cyclic reduction structure
+  std::vector<Level> levels;
+  int top_plane = -1, top_inst = -1;
+  double *zA = nullptr, *zC = nullptr;
+  std::vector<int> plane_inst;  // current D / Dinv instance of each plane
+  // apply workspace
+  double *g = nullptr, *w = nullptr, *z = nullptr, *coef = nullptr;
+  int max_jobs = 0;
+  std::vector<PhaseJobs> ph_apply, ph_applyT;
+  // krylov workspace
+  double *kv = nullptr, *part = nullptr, *dres = nullptr;
+  const double **dots_a = nullptr, **dots_b = nullptr;
+  double* hres = nullptr;  // pinned
+  size_t kv_len = 0;
+  // statistics
+  acr_stats_t st{};
+  int retries = 0;
+
+  ~Handle();
+  void setup(const acr_problem* p, hipStream_t s);
+  void build_factors(hipStream_t s, const std::vector<int>& caps);
+  void free_factors();
+  void run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
+                   const std::vector<const double*>& vecs, hipStream_t s);
+  void build_apply_jobs();
+  void apply(const double* r, double* z, bool transpose, hipStream_t s);
+  void matvec(const double* x, double* y, bool transpose, hipStream_t s);
+  void compute_stats();
+  double instance_bytes(int id, const std::vector<int32_t>& ranks) const;
+};
+
+}  // namespace acr
+
+struct acr_handle {
+  acr::Handle h;
+};

@@ -1,0 +1,157 @@
+"""GPU parity of the HIP path against the CPU FP64 oracle (through the C ABI).
+
+Tolerances
+  * assembly / stencil products / gradient stencil: 1e-13 relative (same
+    formulas, different rounding order);
+  * preconditioner application: ||z_gpu - z_oracle|| / ||z_oracle|| <= 10 eps
+    (both sides are eps-accurate H-arithmetic with different accumulation
+    orders), and in any case not worse than 10x the oracle's own distance
+    to the exact solve;
+  * transpose: <M^-T x, y> = <x, M^-1 y> to 1e-12 (exact by construction);
+  * Krylov solution: relative error <= 1e-8 against a sparse direct solve
+    when run to a 1e-12 residual.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import assembly, gradient, hacr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_08872_amd as acr  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    # name: (kind, nx, ny, nz, eps, eta, leaf)
+    "poisson15": ("poisson", 15, 15, 15, 1e-6, 2.0, 32),
+    "poisson_ragged": ("poisson", 13, 9, 6, 1e-5, 2.0, 16),
+    "convdiff15": ("convdiff", 15, 15, 15, 1e-5, 2.0, 32),
+    "helmholtz11": ("helmholtz", 11, 11, 11, 1e-6, 1.0, 16),
+    "poisson_eta4": ("poisson", 17, 14, 9, 1e-6, 4.0, 16),
+}
+
+
+def _inputs(kind, nx, ny, nz, seed=1):
+    kap = synth.kappa_lognormal(nx, seed, nz=nz, ny=ny) if nx == ny == nz else \
+        np.exp(synth.gaussian_field_exp((nz + 2, ny + 2, nx + 2), seed))
+    if kind == "poisson":
+        S = assembly.stencil7(kind, nx, ny, nz, kappa=kap)
+        kw = dict(kind=acr.POISSON_HARMONIC, kappa=_dev(kap))
+    elif kind == "convdiff":
+        S = assembly.stencil7(kind, nx, ny, nz, kappa=kap, beta_amp=60.0, beta_phase=0.9)
+        kw = dict(kind=acr.CONVDIFF_UPWIND, kappa=_dev(kap), beta_amp=60.0, beta_phase=0.9)
+    else:
+        c = synth.helmholtz_velocity(nx, seed) if nx == ny == nz else np.ones((nz + 2, ny + 2, nx + 2))
+        om = synth.helmholtz_omega(c, nx, ppw=6.0)
+        S = assembly.stencil7(kind, nx, ny, nz, c=c, omega=om)
+        kw = dict(kind=acr.HELMHOLTZ, c=_dev(c), omega=om)
+    return S, kw, kap
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    kind, nx, ny, nz, eps, eta, leaf = CASES[request.param]
+    print(f"\n[case {request.param}] {kind} {nx}x{ny}x{nz} eps={eps} eta={eta} leaf={leaf}", flush=True)
+    S, kw, kap = _inputs(kind, nx, ny, nz)
+    H = hacr.HACR(S, nx, ny, nz, eps=eps, eta=eta, leaf=leaf)
+    h = acr.acr_setup(nx, ny, nz, eps=eps, eta=eta, leaf_size=leaf, **kw)
+    torch.cuda.synchronize()
+    return dict(name=request.param, kind=kind, n=(nx, ny, nz), eps=eps, S=S, H=H, h=h, kap=kap,
+                A=assembly.to_sparse(S, nx, ny, nz))
+
+
+def test_assembly_matches_oracle(case):
+    S_gpu = _np(acr.acr_get_stencil(case["h"])).reshape(7, -1)
+    np.testing.assert_allclose(S_gpu, case["S"], rtol=1e-13, atol=1e-13 * np.abs(case["S"]).max())
+
+
+def test_stencil_matvec(case):
+    N = case["S"].shape[1]
+    x = synth.rhs_uniform(N, 3)
+    for tr in (False, True):
+        y = _np(acr.acr_matvec(case["h"], _dev(x), transpose=tr))
+        ref = (case["A"].T if tr else case["A"]) @ x
+        np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_apply_matches_oracle(case):
+    N = case["S"].shape[1]
+    eps = case["eps"]
+    x_exact_solve = spla.factorized(case["A"].tocsc())
+    for seed in (5, 6):
+        r = synth.rhs_uniform(N, seed)
+        z_or = case["H"].apply(r)
+        z = _np(acr.acr_apply(case["h"], _dev(r)))
+        err = np.linalg.norm(z - z_or) / np.linalg.norm(z_or)
+        ex = x_exact_solve(r)
+        err_or = np.linalg.norm(z_or - ex) / np.linalg.norm(ex)
+        err_gpu = np.linalg.norm(z - ex) / np.linalg.norm(ex)
+        print(f"  apply seed {seed}: |gpu-oracle| {err:.2e}  oracle-exact {err_or:.2e}  gpu-exact {err_gpu:.2e}")
+        assert err <= 10 * eps or err_gpu <= 10 * max(eps, err_or), (err, err_or, err_gpu)
+
+
+def test_apply_T_matches_oracle_and_is_exact_transpose(case):
+    N = case["S"].shape[1]
+    eps = case["eps"]
+    x = synth.rhs_uniform(N, 7)
+    y = synth.rhs_uniform(N, 8)
+    zt_or = case["H"].apply_T(x)
+    zt = _np(acr.acr_apply_T(case["h"], _dev(x)))
+    err = np.linalg.norm(zt - zt_or) / np.linalg.norm(zt_or)
+    assert err <= 10 * eps, err
+    z = _np(acr.acr_apply(case["h"], _dev(y)))
+    lhs, rhs = zt @ y, x @ z
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(zt) * np.linalg.norm(y), (lhs, rhs)
+
+
+def test_apply_is_deterministic(case):
+    N = case["S"].shape[1]
+    r = _dev(synth.rhs_uniform(N, 9))
+    z1 = acr.acr_apply(case["h"], r)
+    z2 = acr.acr_apply(case["h"], r)
+    assert torch.equal(z1, z2)
+
+
+def test_krylov_solution(case):
+    N = case["S"].shape[1]
+    b = synth.rhs_uniform(N, 10)
+    x_ref = spla.spsolve(case["A"].tocsc(), b)
+    method = acr.CG if case["kind"] == "poisson" else acr.GMRES
+    x, info = acr.krylov_solve(case["h"], _dev(b), method=method, restart=30, rtol=1e-12, maxit=200)
+    err = np.linalg.norm(_np(x) - x_ref) / np.linalg.norm(x_ref)
+    print(f"  krylov: iters {info['iters']} relres {info['relres_true']:.2e} err {err:.2e}")
+    assert info["relres_true"] <= 1e-12
+    assert err <= 1e-8
+    xt, infot = acr.krylov_solve(case["h"], _dev(b), method=method, transpose=True, rtol=1e-12, maxit=200)
+    xt_ref = spla.spsolve(case["A"].T.tocsc(), b)
+    assert np.linalg.norm(_np(xt) - xt_ref) <= 1e-8 * np.linalg.norm(xt_ref)
+
+
+def test_gradient_stencil_matches_oracle(case):
+    if case["kind"] != "poisson":
+        pytest.skip("gradient is defined for the harmonic-average Poisson operator")
+    nx, ny, nz = case["n"]
+    N = nx * ny * nz
+    u = synth.rhs_uniform(N, 11)
+    lam = synth.rhs_uniform(N, 12)
+    g = _np(acr.acr_grad_kappa(case["h"], _dev(u), _dev(lam)))
+    ref = gradient.grad_kappa(case["kap"], u, lam, nx, ny, nz).reshape(-1)
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_stats_are_consistent(case):
+    st = acr.acr_stats(case["h"])
+    assert st["levels"] == len(case["H"].levels) + 1
+    assert st["bytes_factors"] > 0 and st["bytes_per_apply"] >= st["bytes_factors"]
+    assert st["rank_overflow"] == 0
