@@ -46,71 +46,85 @@ __device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
   q = ((Kp - 2 - i + r) % M) + 1;
 }
 
-// Cyclic (parallel-ordered) two-sided Jacobi for a symmetric K x K matrix
-// in LDS (leading dimension KC).  On exit A is (numerically) diagonal and
-// Q holds the eigenvectors (Q must be initialised by the caller).
-__device__ void jacobi_eig(double* A, double* Q, int K, double* cs, int* sflag) {
+// Cyclic two-sided Jacobi for a symmetric K x K matrix in LDS (leading
+// dimension KC), parallel (tournament) ordering: every round rotates K/2
+// disjoint index pairs at once.  The new entries of each 2 x 2 block of
+// pairs depend only on that block, so a round is one read-compute-write
+// phase.  A rotation is skipped when the off-diagonal entry is negligible
+// relative to its diagonal pair or to the largest diagonal entry.  On exit
+// A is numerically diagonal and Q (initialised by the caller) holds the
+// eigenvectors.  `cs` holds 2*(KC/2+1) doubles, `pq` 2*(KC/2+1) ints.
+__device__ void jacobi_eig(double* A, double* Q, int K, double* cs, int* pq, int* sflag, double* amax_s) {
   const int tid = threadIdx.x;
+  if (K <= 1) return;
   const int Kp = K + (K & 1);
   const int np = Kp / 2;
-  if (K <= 1) return;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) *sflag = 0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) {
+      double amax = 0.0;
+      for (int i = 0; i < K; ++i) amax = fmax(amax, fabs(A[i * KC + i]));
+      *amax_s = amax;
+      *sflag = 0;
+    }
     __syncthreads();
+    const double atol = 1e-18 * (*amax_s);
     for (int r = 0; r < Kp - 1; ++r) {
       if (tid < np) {
         int p, q;
         rr_pair(Kp, r, tid, p, q);
+        if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
-        if (p < K && q < K) {
-          if (p > q) { int t = p; p = q; q = t; }
-          double apq = A[p * KC + q];
-          double app = A[p * KC + p], aqq = A[q * KC + q];
-          if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
-            double tau = (aqq - app) / (2.0 * apq);
-            double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        if (q >= K) {
+          q = -1;  // partner is the padding index
+        } else {
+          const double apq = A[p * KC + q];
+          const double app = A[p * KC + p], aqq = A[q * KC + q];
+          if (fabs(apq) > atol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
             *sflag = 1;
           }
-        } else {
-          p = q = -1;
         }
-        cs[4 * tid + 0] = c;
-        cs[4 * tid + 1] = s;
-        cs[4 * tid + 2] = (double)p;
-        cs[4 * tid + 3] = (double)q;
+        cs[2 * tid] = c;
+        cs[2 * tid + 1] = s;
+        pq[2 * tid] = p;
+        pq[2 * tid + 1] = q;
       }
       __syncthreads();
-      // rows p, q  <-  J^T A
-      for (int idx = tid; idx < np * K; idx += blockDim.x) {
-        int pi = idx / K, j = idx - pi * K;
-        int p = (int)cs[4 * pi + 2], q = (int)cs[4 * pi + 3];
-        double s = cs[4 * pi + 1];
-        if (p < 0 || s == 0.0) continue;
-        double c = cs[4 * pi];
-        double ap = A[p * KC + j], aq = A[q * KC + j];
-        A[p * KC + j] = c * ap - s * aq;
-        A[q * KC + j] = s * ap + c * aq;
+      // A <- J^T A J on 2 x 2 blocks of pairs
+      for (int blk = tid; blk < np * np; blk += TPB) {
+        const int pi = blk / np, pj = blk - pi * np;
+        const double s1 = cs[2 * pi + 1], s2 = cs[2 * pj + 1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const double c1 = cs[2 * pi], c2 = cs[2 * pj];
+        const int p1 = pq[2 * pi], q1 = pq[2 * pi + 1], p2 = pq[2 * pj], q2 = pq[2 * pj + 1];
+        const double a11 = A[p1 * KC + p2];
+        const double a12 = q2 >= 0 ? A[p1 * KC + q2] : 0.0;
+        const double a21 = q1 >= 0 ? A[q1 * KC + p2] : 0.0;
+        const double a22 = (q1 >= 0 && q2 >= 0) ? A[q1 * KC + q2] : 0.0;
+        const double r11 = c1 * a11 - s1 * a21, r12 = c1 * a12 - s1 * a22;
+        const double r21 = s1 * a11 + c1 * a21, r22 = s1 * a12 + c1 * a22;
+        A[p1 * KC + p2] = c2 * r11 - s2 * r12;
+        if (q2 >= 0) A[p1 * KC + q2] = s2 * r11 + c2 * r12;
+        if (q1 >= 0) A[q1 * KC + p2] = c2 * r21 - s2 * r22;
+        if (q1 >= 0 && q2 >= 0) A[q1 * KC + q2] = s2 * r21 + c2 * r22;
       }
-      __syncthreads();
-      // columns p, q  <-  A J ;  Q <- Q J
-      for (int idx = tid; idx < np * K; idx += blockDim.x) {
-        int pi = idx / K, i = idx - pi * K;
-        int p = (int)cs[4 * pi + 2], q = (int)cs[4 * pi + 3];
-        double s = cs[4 * pi + 1];
-        if (p < 0 || s == 0.0) continue;
-        double c = cs[4 * pi];
-        double ap = A[i * KC + p], aq = A[i * KC + q];
-        A[i * KC + p] = c * ap - s * aq;
-        A[i * KC + q] = s * ap + c * aq;
-        double qp = Q[i * KC + p], qq = Q[i * KC + q];
-        Q[i * KC + p] = c * qp - s * qq;
-        Q[i * KC + q] = s * qp + c * qq;
+      // Q <- Q J
+      for (int it = tid; it < K * np; it += TPB) {
+        const int i = it / np, pj = it - i * np;
+        const double s2 = cs[2 * pj + 1];
+        if (s2 == 0.0) continue;
+        const double c2 = cs[2 * pj];
+        const int p2 = pq[2 * pj], q2 = pq[2 * pj + 1];
+        const double qp = Q[i * KC + p2], qq = Q[i * KC + q2];
+        Q[i * KC + p2] = c2 * qp - s2 * qq;
+        Q[i * KC + q2] = s2 * qp + c2 * qq;
       }
       __syncthreads();
     }
-    int f = *sflag;
+    const int f = *sflag;
     __syncthreads();
     if (!f) break;
   }
@@ -122,9 +136,11 @@ struct Lds {
   double S2[KC * KC];
   double S3[KC * KC];
   double v0[KC], v1[KC], v2[KC], v3[KC];
-  double cs[4 * (KC / 2 + 1)];
+  double cs[2 * (KC / 2 + 1)];
+  int pq[2 * (KC / 2 + 1)];
   int keep[KC], order[KC];
   int ival[8];
+  double dval[4];
 };
 
 // Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
@@ -211,7 +227,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     L.S1[i * KC + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_eig(L.S0, L.S1, K, L.cs, &L.ival[0]);
+  jacobi_eig(L.S0, L.S1, K, L.cs, L.pq, &L.ival[0], &L.dval[0]);
   // eigenvalues of G_V; keep the numerically non-zero ones
   if (tid == 0) {
     double lmax = 0.0;
@@ -262,7 +278,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     L.S1[a * KC + c] = (a == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_eig(L.S0, L.S1, Kp, L.cs, &L.ival[0]);
+  jacobi_eig(L.S0, L.S1, Kp, L.cs, L.pq, &L.ival[0], &L.dval[0]);
   // singular values, descending order, truncation rank
   if (tid < Kp) L.v2[tid] = sqrt(fmax(L.S0[tid * KC + tid], 0.0));
   __syncthreads();
@@ -335,12 +351,83 @@ __device__ int piece_width(const AccumArgs<T>& A, int b, const Piece& P) {
   return 0;
 }
 
+// Out[i][j] = sum_q P[q + i*ldp] * R[q + j*ldr] for i < mo, j < no (both
+// operands contiguous along q), staged through LDS in chunks of KC along q.
+// Out is LDS with leading dimension KC; mo, no <= KC.
+template <typename T>
+__device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no, double* Out,
+                           double* bP, double* bR) {
+  const int tid = threadIdx.x;
+  constexpr int PER = KC * KC / TPB;
+  double acc[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) acc[e] = 0.0;
+  for (int q0 = 0; q0 < nq; q0 += KC) {
+    const int nqq = imin(KC, nq - q0);
+    for (int idx = tid; idx < nqq * mo; idx += TPB) {
+      const int q = idx % nqq, i = idx / nqq;
+      bP[q * KC + i] = (double)P[q0 + q + (int64_t)i * ldp];
+    }
+    for (int idx = tid; idx < nqq * no; idx += TPB) {
+      const int q = idx % nqq, j = idx / nqq;
+      bR[q * KC + j] = (double)R[q0 + q + (int64_t)j * ldr];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + e * TPB;
+      if (idx < mo * no) {
+        const int i = idx / no, j = idx - i * no;
+        double s = 0.0;
+        for (int q = 0; q < nqq; ++q) s += bP[q * KC + i] * bR[q * KC + j];
+        acc[e] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int idx = tid + e * TPB;
+    if (idx < mo * no) {
+      const int i = idx / no, j = idx - i * no;
+      Out[i * KC + j] = acc[e];
+    }
+  }
+  __syncthreads();
+}
+
+// dst[i*drs + j*dcs] += alpha * sum_a M[i + a*ldm] * Z[a*KC + j] for i < mi,
+// a < na (<= KC), j < no (<= KC); M contiguous along i, Z in LDS.  `bM` is
+// an LDS staging buffer of KC x KC doubles.
+template <typename T>
+__device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const double* Z, int no, T* dst, int64_t drs,
+                       int64_t dcs, double alpha, double* bM) {
+  const int tid = threadIdx.x;
+  for (int i0 = 0; i0 < mi; i0 += KC) {
+    const int ni = imin(KC, mi - i0);
+    for (int idx = tid; idx < ni * na; idx += TPB) {
+      const int ii = idx % ni, a = idx / ni;
+      bM[a * KC + ii] = (double)M[(i0 + ii) + (int64_t)a * ldm];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < ni * no; idx += TPB) {
+      const int j = idx % no, ii = idx / no;
+      double s = 0.0;
+      for (int a = 0; a < na; ++a) s += bM[a * KC + ii] * Z[a * KC + j];
+      T* d = dst + (int64_t)(i0 + ii) * drs + (int64_t)j * dcs;
+      *d = (T)((double)*d + alpha * s);
+    }
+    __syncthreads();
+  }
+}
+
 // Write columns [j0, j0+take) of a piece into scratch columns [K, K+take)
 // of Us (target rows) and Vs (target columns), row-major ld KC.  The alpha
-// of the piece is folded into Us.
+// of the piece is folded into Us.  LDS buffers S0 (products), S1, S2
+// (staging) are used.
 template <typename T>
-__device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0,
-                              int take, T* Us, T* Vs, int K, double* Z) {
+__device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0, int take,
+                              T* Us, T* Vs, int K, Lds& L) {
   const int tid = threadIdx.x;
   const int m = tc.m, n = tc.n;
   const double alpha = P.alpha;
@@ -350,13 +437,14 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const T* Ux = leaf_base(A, xi, P.xleaf);
     const T* Vx = Ux + (int64_t)x.m * x.cap;
     for (int idx = tid; idx < m * take; idx += TPB) {
-      int i = idx / take, jj = idx - i * take;
-      int gi = tc.r0 + i;
-      double v = (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * x.m] : 0.0;
+      const int i = idx / take, jj = idx - i * take;
+      const int gi = tc.r0 + i;
+      const double v =
+          (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * x.m] : 0.0;
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
-      int c = idx / take, jj = idx - c * take;
+      const int c = idx / take, jj = idx - c * take;
       Vs[(int64_t)c * KC + K + jj] = (T)0;
     }
     __syncthreads();
@@ -364,47 +452,32 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int l = A.lists[li];
       const DLeaf lam = A.leaves[l];
       const int cA = imax(lam.c0, P.wc0), cB = imin(lam.c0 + lam.n, P.wc1);
-      if (cA >= cB) continue;
-      const T* lp = leaf_base(A, yi, l);
-      // middle index range shared by lam's rows and x's columns
       const int q0 = imax(lam.r0, x.c0), q1 = imin(lam.r0 + lam.m, x.c0 + x.n);
-      if (q0 >= q1) continue;
+      if (cA >= cB || q0 >= q1) continue;
       const int nq = q1 - q0;
+      const T* lp = leaf_base(A, yi, l);
+      const T* vx = Vx + (q0 - x.c0) + (int64_t)j0 * x.n;
       if (lam.fmt == 0) {
-        for (int idx = tid; idx < (cB - cA) * take; idx += TPB) {
-          int cc = idx / take, jj = idx - cc * take;
-          int c = cA + cc;
-          const T* col = lp + (int64_t)(c - lam.c0) * lam.m + (q0 - lam.r0);
-          const T* vx = Vx + (q0 - x.c0) + (int64_t)(j0 + jj) * x.n;
-          double s = 0.0;
-          for (int r = 0; r < nq; ++r) s += (double)col[r] * (double)vx[r];
-          T* dst = &Vs[(int64_t)(c - tc.c0) * KC + K + jj];
-          *dst = (T)((double)*dst + s);
+        for (int c0 = cA; c0 < cB; c0 += KC) {
+          const int nc = imin(KC, cB - c0);
+          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lam.m, lam.m, vx, x.n, nq, nc, take, L.S0, L.S1,
+                     L.S2);
+          for (int idx = tid; idx < nc * take; idx += TPB) {
+            const int cc = idx / take, jj = idx - cc * take;
+            T* d = &Vs[(int64_t)(c0 + cc - tc.c0) * KC + K + jj];
+            *d = (T)((double)*d + L.S0[cc * KC + jj]);
+          }
+          __syncthreads();
         }
       } else {
         const int kl = rank_of(A, yi, l);
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lp + (int64_t)lam.m * lam.cap;
-        for (int idx = tid; idx < kl * take; idx += TPB) {
-          int a = idx / take, jj = idx - a * take;
-          const T* ua = Ul + (int64_t)a * lam.m + (q0 - lam.r0);
-          const T* vx = Vx + (q0 - x.c0) + (int64_t)(j0 + jj) * x.n;
-          double s = 0.0;
-          for (int r = 0; r < nq; ++r) s += (double)ua[r] * (double)vx[r];
-          Z[a * KC + jj] = s;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < (cB - cA) * take; idx += TPB) {
-          int cc = idx / take, jj = idx - cc * take;
-          int c = cA + cc;
-          double s = 0.0;
-          for (int a = 0; a < kl; ++a) s += (double)Vl[(c - lam.c0) + (int64_t)a * lam.n] * Z[a * KC + jj];
-          T* dst = &Vs[(int64_t)(c - tc.c0) * KC + K + jj];
-          *dst = (T)((double)*dst + s);
-        }
+        tn_product(Ul + (q0 - lam.r0), lam.m, vx, x.n, nq, kl, take, L.S0, L.S1, L.S2);
+        nn_acc(Vl + (cA - lam.c0), lam.n, cB - cA, kl, L.S0, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
+               L.S1);
       }
-      __syncthreads();
     }
   } else if (P.kind == PK_LRY) {
     const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
@@ -412,13 +485,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const T* Uy = leaf_base(A, yi, P.yleaf);
     const T* Vy = Uy + (int64_t)y.m * y.cap;
     for (int idx = tid; idx < n * take; idx += TPB) {
-      int c = idx / take, jj = idx - c * take;
-      int gc = tc.c0 + c;
-      double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * y.n] : 0.0;
+      const int c = idx / take, jj = idx - c * take;
+      const int gc = tc.c0 + c;
+      const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * y.n] : 0.0;
       Vs[(int64_t)c * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < m * take; idx += TPB) {
-      int i = idx / take, jj = idx - i * take;
+      const int i = idx / take, jj = idx - i * take;
       Us[(int64_t)i * KC + K + jj] = (T)0;
     }
     __syncthreads();
@@ -426,47 +499,31 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int l = A.lists[li];
       const DLeaf lam = A.leaves[l];
       const int rA = imax(lam.r0, P.wr0), rB = imin(lam.r0 + lam.m, P.wr1);
-      if (rA >= rB) continue;
-      const T* lp = leaf_base(A, xi, l);
-      // middle index range shared by lam's columns and y's rows
       const int q0 = imax(lam.c0, y.r0), q1 = imin(lam.c0 + lam.n, y.r0 + y.m);
-      if (q0 >= q1) continue;
+      if (rA >= rB || q0 >= q1) continue;
       const int nq = q1 - q0;
+      const T* lp = leaf_base(A, xi, l);
+      const T* uy = Uy + (q0 - y.r0) + (int64_t)j0 * y.m;
       if (lam.fmt == 0) {
-        for (int idx = tid; idx < (rB - rA) * take; idx += TPB) {
-          int ii = idx / take, jj = idx - ii * take;
-          int i = rA + ii;
-          const T* uy = Uy + (q0 - y.r0) + (int64_t)(j0 + jj) * y.m;
-          const T* row = lp + (i - lam.r0) + (int64_t)(q0 - lam.c0) * lam.m;
-          double s = 0.0;
-          for (int q = 0; q < nq; ++q) s += (double)row[(int64_t)q * lam.m] * (double)uy[q];
-          T* dst = &Us[(int64_t)(i - tc.r0) * KC + K + jj];
-          *dst = (T)((double)*dst + alpha * s);
+        for (int qc = 0; qc < nq; qc += KC) {
+          const int nqc = imin(KC, nq - qc);
+          for (int idx = tid; idx < nqc * take; idx += TPB) {
+            const int q = idx % nqc, jj = idx / nqc;
+            L.S0[q * KC + jj] = (double)uy[qc + q + (int64_t)jj * y.m];
+          }
+          __syncthreads();
+          nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lam.m, lam.m, rB - rA, nqc, L.S0, take,
+                 Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, L.S1);
         }
       } else {
         const int kl = rank_of(A, xi, l);
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lp + (int64_t)lam.m * lam.cap;
-        for (int idx = tid; idx < kl * take; idx += TPB) {
-          int a = idx / take, jj = idx - a * take;
-          const T* va = Vl + (int64_t)a * lam.n + (q0 - lam.c0);
-          const T* uy = Uy + (q0 - y.r0) + (int64_t)(j0 + jj) * y.m;
-          double s = 0.0;
-          for (int q = 0; q < nq; ++q) s += (double)va[q] * (double)uy[q];
-          Z[a * KC + jj] = s;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < (rB - rA) * take; idx += TPB) {
-          int ii = idx / take, jj = idx - ii * take;
-          int i = rA + ii;
-          double s = 0.0;
-          for (int a = 0; a < kl; ++a) s += (double)Ul[(i - lam.r0) + (int64_t)a * lam.m] * Z[a * KC + jj];
-          T* dst = &Us[(int64_t)(i - tc.r0) * KC + K + jj];
-          *dst = (T)((double)*dst + alpha * s);
-        }
+        tn_product(Vl + (q0 - lam.c0), lam.n, uy, y.m, nq, kl, take, L.S0, L.S1, L.S2);
+        nn_acc(Ul + (rA - lam.r0), lam.m, rB - rA, kl, L.S0, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
+               L.S1);
       }
-      __syncthreads();
     }
   } else if (P.kind == PK_DD) {
     // dense product into a low-rank target: U-part = alpha P[:, cols], V-part = selector
@@ -476,18 +533,23 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const T* yp = leaf_base(A, yi, P.yleaf);
     const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
     for (int idx = tid; idx < m * take; idx += TPB) {
-      int i = idx / take, jj = idx - i * take;
-      int gi = tc.r0 + i, gc = P.wc0 + j0 + jj;
-      double s = 0.0;
-      if (gi >= P.wr0 && gi < P.wr1) {
-        for (int q = M0; q < M1; ++q)
-          s += (double)xp[(gi - x.r0) + (int64_t)(q - x.c0) * x.m] * (double)yp[(q - y.r0) + (int64_t)(gc - y.c0) * y.m];
-      }
-      Us[(int64_t)i * KC + K + jj] = (T)(alpha * s);
+      const int i = idx / take, jj = idx - i * take;
+      Us[(int64_t)i * KC + K + jj] = (T)0;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
-      int c = idx / take, jj = idx - c * take;
+      const int c = idx / take, jj = idx - c * take;
       Vs[(int64_t)c * KC + K + jj] = (T)((tc.c0 + c == P.wc0 + j0 + jj) ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int qc = M0; qc < M1; qc += KC) {
+      const int nqc = imin(KC, M1 - qc);
+      for (int idx = tid; idx < nqc * take; idx += TPB) {
+        const int q = idx % nqc, jj = idx / nqc;
+        L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(P.wc0 + j0 + jj - y.c0) * y.m];
+      }
+      __syncthreads();
+      nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, take,
+             Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, L.S1);
     }
   } else {  // PK_COPY of a low-rank leaf
     const int si = inst_of(A, b, P.xrole);
@@ -497,13 +559,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
     const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
     for (int idx = tid; idx < m * take; idx += TPB) {
-      int i = idx / take, jj = idx - i * take;
+      const int i = idx / take, jj = idx - i * take;
       double v = alpha * (double)Usrc[i + (int64_t)(j0 + jj) * s.m];
       if (rho) v *= rho[tc.r0 + i];
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
-      int c = idx / take, jj = idx - c * take;
+      const int c = idx / take, jj = idx - c * take;
       double v = (double)Vsrc[c + (int64_t)(j0 + jj) * s.n];
       if (gam) v *= gam[tc.c0 + c];
       Vs[(int64_t)c * KC + K + jj] = (T)v;
@@ -512,17 +574,33 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
   __syncthreads();
 }
 
-// Dense target: C[win] += Us Vs^T for `take` columns.
+// Dense target: C += Us Vs^T for `take` columns (C column-major m x n).
 template <typename T>
-__device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take) {
+__device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, Lds& L) {
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
-    int i = idx % tc.m, c = idx / tc.m;
-    double s = 0.0;
-    for (int jj = 0; jj < take; ++jj) s += (double)Us[(int64_t)i * KC + jj] * (double)Vs[(int64_t)c * KC + jj];
-    C[idx] = (T)((double)C[idx] + s);
+  for (int c0 = 0; c0 < tc.n; c0 += KC) {
+    const int nc = imin(KC, tc.n - c0);
+    for (int idx = tid; idx < nc * take; idx += TPB) {
+      const int jj = idx % take, cc = idx / take;
+      L.S0[jj * KC + cc] = (double)Vs[(int64_t)(c0 + cc) * KC + jj];
+    }
+    for (int i0 = 0; i0 < tc.m; i0 += KC) {
+      const int ni = imin(KC, tc.m - i0);
+      for (int idx = tid; idx < ni * take; idx += TPB) {
+        const int jj = idx % take, ii = idx / take;
+        L.S1[jj * KC + ii] = (double)Us[(int64_t)(i0 + ii) * KC + jj];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < ni * nc; idx += TPB) {
+        const int ii = idx % ni, cc = idx / ni;
+        double s = 0.0;
+        for (int jj = 0; jj < take; ++jj) s += L.S1[jj * KC + ii] * L.S0[jj * KC + cc];
+        T* d = &C[(i0 + ii) + (int64_t)(c0 + cc) * tc.m];
+        *d = (T)((double)*d + s);
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
 }
 
 // ------------------------------------------------------------ main kernel
@@ -554,16 +632,19 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           const T* xp = leaf_base(A, xi, P.xleaf);
           const T* yp = leaf_base(A, yi, P.yleaf);
           const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
-          const int wr = P.wr1 - P.wr0, wc = P.wc1 - P.wc0;
-          for (int idx = tid; idx < wr * wc; idx += TPB) {
-            int gi = P.wr0 + idx % wr, gc = P.wc0 + idx / wr;
-            double s = 0.0;
-            for (int q = M0; q < M1; ++q)
-              s += (double)xp[(gi - x.r0) + (int64_t)(q - x.c0) * x.m] * (double)yp[(q - y.r0) + (int64_t)(gc - y.c0) * y.m];
-            T* dst = &C[(gi - tc.r0) + (int64_t)(gc - tc.c0) * tc.m];
-            *dst = (T)((double)*dst + P.alpha * s);
+          for (int cc0 = P.wc0; cc0 < P.wc1; cc0 += KC) {
+            const int nc = imin(KC, P.wc1 - cc0);
+            for (int qc = M0; qc < M1; qc += KC) {
+              const int nqc = imin(KC, M1 - qc);
+              for (int idx = tid; idx < nqc * nc; idx += TPB) {
+                const int q = idx % nqc, jj = idx / nqc;
+                L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * y.m];
+              }
+              __syncthreads();
+              nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, nc,
+                     C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
+            }
           }
-          __syncthreads();
         } else if (P.kind == PK_COPY) {
           const int si = inst_of(A, b, P.xrole);
           if (si < 0) continue;
@@ -582,8 +663,8 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           const int w = piece_width(A, b, P);
           for (int j0 = 0; j0 < w; j0 += KC) {
             int take = imin(KC, w - j0);
-            piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L.S0);
-            dense_add_outer(C, tc, Us, Vs, take);
+            piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
+            dense_add_outer(C, tc, Us, Vs, take, L);
           }
         }
       }
@@ -645,7 +726,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           }
         }
         int take = imin(w - j0, KC - K);
-        piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L.S0);
+        piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
         K += take;
         j0 += take;
       }
