@@ -3,14 +3,17 @@
 // the level-0 conversion of the plane operators.
 //
 // Truncation T_eps (Sec. 3.1.5, Sec. 4.3 of the paper: block-wise relative
-// accuracy, singular values sigma_i > eps sigma_1 kept): for a block given
-// as U V^T with K columns (the block's current factors concatenated with
-// the incoming contributions), the columns are norm-balanced, the Gram
-// matrices G_U = U^T U and G_V = V^T V are formed in FP64, G_V = Q L Q^T by
-// cyclic Jacobi, M = (Q L^1/2)^T G_U (Q L^1/2) = W S^2 W^T by cyclic Jacobi,
-// and U' = U Q L^1/2 W_k, V' = V Q L^-1/2 W_k.  This is the truncated SVD of
-// U V^T expressed through K x K eigenproblems; it resolves singular values
-// down to about 1e-8 sigma_1 (square root of FP64 round-off).
+// accuracy, singular values sigma_i > eps sigma_1 kept) of a block given as
+// U V^T with K columns (the block's current factors concatenated with the
+// incoming contributions): the column pairs are norm-balanced, the Gram
+// matrices G_U = U^T U and G_V = V^T V are formed in FP64, each is factored
+// by Cholesky with symmetric pivoting, stopped at its numerical rank
+// (G = P R^T R P^T, so U = Q_U R_U P^T with Q_U = U_piv R_U11^-1), the small
+// core R_U P_U^T P_V R_V^T is diagonalised by one-sided (Hestenes) Jacobi,
+// and U' = Q_U W_k S_k, V' = Q_V Z_k are formed by triangular solves and one
+// product with the concatenated factors.  This is the truncated SVD of
+// U V^T; through the Gram matrices it resolves singular values down to
+// about 1e-8 sigma_1.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -46,99 +49,13 @@ __device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
   q = ((Kp - 2 - i + r) % M) + 1;
 }
 
-// Cyclic two-sided Jacobi for a symmetric K x K matrix in LDS (leading
-// dimension KC), parallel (tournament) ordering: every round rotates K/2
-// disjoint index pairs at once.  The new entries of each 2 x 2 block of
-// pairs depend only on that block, so a round is one read-compute-write
-// phase.  A rotation is skipped when the off-diagonal entry is negligible
-// relative to its diagonal pair or to the largest diagonal entry.  On exit
-// A is numerically diagonal and Q (initialised by the caller) holds the
-// eigenvectors.  `cs` holds 2*(KC/2+1) doubles, `pq` 2*(KC/2+1) ints.
-__device__ void jacobi_eig(double* A, double* Q, int K, double* cs, int* pq, int* sflag, double* amax_s) {
-  const int tid = threadIdx.x;
-  if (K <= 1) return;
-  const int Kp = K + (K & 1);
-  const int np = Kp / 2;
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) {
-      double amax = 0.0;
-      for (int i = 0; i < K; ++i) amax = fmax(amax, fabs(A[i * KC + i]));
-      *amax_s = amax;
-      *sflag = 0;
-    }
-    __syncthreads();
-    const double atol = 1e-18 * (*amax_s);
-    for (int r = 0; r < Kp - 1; ++r) {
-      if (tid < np) {
-        int p, q;
-        rr_pair(Kp, r, tid, p, q);
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q >= K) {
-          q = -1;  // partner is the padding index
-        } else {
-          const double apq = A[p * KC + q];
-          const double app = A[p * KC + p], aqq = A[q * KC + q];
-          if (fabs(apq) > atol && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            *sflag = 1;
-          }
-        }
-        cs[2 * tid] = c;
-        cs[2 * tid + 1] = s;
-        pq[2 * tid] = p;
-        pq[2 * tid + 1] = q;
-      }
-      __syncthreads();
-      // A <- J^T A J on 2 x 2 blocks of pairs
-      for (int blk = tid; blk < np * np; blk += TPB) {
-        const int pi = blk / np, pj = blk - pi * np;
-        const double s1 = cs[2 * pi + 1], s2 = cs[2 * pj + 1];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const double c1 = cs[2 * pi], c2 = cs[2 * pj];
-        const int p1 = pq[2 * pi], q1 = pq[2 * pi + 1], p2 = pq[2 * pj], q2 = pq[2 * pj + 1];
-        const double a11 = A[p1 * KC + p2];
-        const double a12 = q2 >= 0 ? A[p1 * KC + q2] : 0.0;
-        const double a21 = q1 >= 0 ? A[q1 * KC + p2] : 0.0;
-        const double a22 = (q1 >= 0 && q2 >= 0) ? A[q1 * KC + q2] : 0.0;
-        const double r11 = c1 * a11 - s1 * a21, r12 = c1 * a12 - s1 * a22;
-        const double r21 = s1 * a11 + c1 * a21, r22 = s1 * a12 + c1 * a22;
-        A[p1 * KC + p2] = c2 * r11 - s2 * r12;
-        if (q2 >= 0) A[p1 * KC + q2] = s2 * r11 + c2 * r12;
-        if (q1 >= 0) A[q1 * KC + p2] = c2 * r21 - s2 * r22;
-        if (q1 >= 0 && q2 >= 0) A[q1 * KC + q2] = s2 * r21 + c2 * r22;
-      }
-      // Q <- Q J
-      for (int it = tid; it < K * np; it += TPB) {
-        const int i = it / np, pj = it - i * np;
-        const double s2 = cs[2 * pj + 1];
-        if (s2 == 0.0) continue;
-        const double c2 = cs[2 * pj];
-        const int p2 = pq[2 * pj], q2 = pq[2 * pj + 1];
-        const double qp = Q[i * KC + p2], qq = Q[i * KC + q2];
-        Q[i * KC + p2] = c2 * qp - s2 * qq;
-        Q[i * KC + q2] = s2 * qp + c2 * qq;
-      }
-      __syncthreads();
-    }
-    const int f = *sflag;
-    __syncthreads();
-    if (!f) break;
-  }
-}
-
 struct Lds {
   double S0[KC * KC];
   double S1[KC * KC];
   double S2[KC * KC];
   double S3[KC * KC];
-  double v0[KC], v1[KC], v2[KC], v3[KC];
-  double cs[2 * (KC / 2 + 1)];
-  int pq[2 * (KC / 2 + 1)];
-  int keep[KC], order[KC];
+  double v0[KC], v1[KC];
+  int permU[KC], permV[KC], posU[KC], posV[KC], order[KC];
   int ival[8];
   double dval[4];
 };
@@ -202,126 +119,249 @@ __device__ void rebuild(T* X, int rows, int K, int k, const double* R, double* t
   }
 }
 
+// Cholesky factorisation with symmetric pivoting of the K x K symmetric
+// positive semi-definite G (LDS, ld KC), in place: on exit the rows a < r
+// of the upper trapezoid hold R (pivot order), perm[a] is the original
+// index of pivot a, pos[] its inverse.  Stops when the largest remaining
+// diagonal entry is <= rel_tol times the largest initial one; returns r.
+__device__ int pivoted_cholesky(double* G, int K, int* perm, int* pos, int* ival, double* dval, double rel_tol) {
+  const int tid = threadIdx.x;
+  if (tid < K) perm[tid] = tid;
+  if (tid == 0) {
+    double d0 = 0.0;
+    for (int i = 0; i < K; ++i) d0 = fmax(d0, G[i * KC + i]);
+    dval[0] = rel_tol * d0;
+  }
+  __syncthreads();
+  const double tol = dval[0];
+  int r = 0;
+  for (int a = 0; a < K; ++a) {
+    if (tid == 0) {
+      int p = a;
+      double dm = G[a * KC + a];
+      for (int i = a + 1; i < K; ++i)
+        if (G[i * KC + i] > dm) { dm = G[i * KC + i]; p = i; }
+      ival[0] = p;
+      ival[1] = (dm > tol && dm > 0.0) ? 1 : 0;
+      if (ival[1] && p != a) { int t = perm[a]; perm[a] = perm[p]; perm[p] = t; }
+    }
+    __syncthreads();
+    if (!ival[1]) break;
+    const int p = ival[0];
+    if (p != a) {
+      for (int j = tid; j < K; j += TPB) {
+        double t = G[a * KC + j]; G[a * KC + j] = G[p * KC + j]; G[p * KC + j] = t;
+      }
+      __syncthreads();
+      for (int i = tid; i < K; i += TPB) {
+        double t = G[i * KC + a]; G[i * KC + a] = G[i * KC + p]; G[i * KC + p] = t;
+      }
+      __syncthreads();
+    }
+    const double rd = sqrt(G[a * KC + a]);
+    __syncthreads();
+    for (int j = a + tid; j < K; j += TPB) G[a * KC + j] = (j == a) ? rd : G[a * KC + j] / rd;
+    __syncthreads();
+    const int rem = K - a - 1;
+    for (int idx = tid; idx < rem * rem; idx += TPB) {
+      const int i = a + 1 + idx / rem, j = a + 1 + idx % rem;
+      G[i * KC + j] -= G[a * KC + i] * G[a * KC + j];
+    }
+    __syncthreads();
+    r = a + 1;
+  }
+  if (tid < K) pos[perm[tid]] = tid;
+  __syncthreads();
+  return r;
+}
+
+// One-sided Jacobi (Hestenes) on the columns of C (rows x cols, LDS ld KC):
+// C <- C Z with orthogonal columns, Z accumulated (initialised by the
+// caller).  Pairs of columns are processed in tournament order, one pair per
+// group of 8 lanes, dot products reduced with lane shuffles.
+__device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sflag, double* dval) {
+  const int tid = threadIdx.x;
+  if (cols <= 1) return 0;
+  const int Kp = cols + (cols & 1), np = Kp / 2;
+  const int g = tid >> 3, l = tid & 7;
+  // pairs whose inner product is below 1e-18 ||C||_F^2 are orthogonal for
+  // every singular value the truncation can keep
+  if (tid == 0) {
+    double f = 0.0;
+    for (int i = 0; i < rows; ++i)
+      for (int j = 0; j < cols; ++j) f += C[i * KC + j] * C[i * KC + j];
+    dval[1] = 1e-18 * f;
+  }
+  __syncthreads();
+  const double cabs = dval[1];
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
+    if (tid == 0) *sflag = 0;
+    __syncthreads();
+    for (int r = 0; r < Kp - 1; ++r) {
+      if (g < np) {
+        int p, q;
+        rr_pair(Kp, r, g, p, q);
+        if (q < cols && p < cols) {
+          double a = 0.0, b = 0.0, c = 0.0;
+          for (int i = l; i < rows; i += 8) {
+            const double x = C[i * KC + p], y = C[i * KC + q];
+            a += x * x;
+            b += y * y;
+            c += x * y;
+          }
+#pragma unroll
+          for (int o = 1; o < 8; o <<= 1) {
+            a += __shfl_xor(a, o);
+            b += __shfl_xor(b, o);
+            c += __shfl_xor(c, o);
+          }
+          if (fabs(c) > 1e-15 * sqrt(a * b) && fabs(c) > cabs) {
+            const double zeta = (b - a) / (2.0 * c);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            for (int i = l; i < rows; i += 8) {
+              const double x = C[i * KC + p], y = C[i * KC + q];
+              C[i * KC + p] = cs * x - sn * y;
+              C[i * KC + q] = sn * x + cs * y;
+            }
+            for (int i = l; i < cols; i += 8) {
+              const double x = Z[i * KC + p], y = Z[i * KC + q];
+              Z[i * KC + p] = cs * x - sn * y;
+              Z[i * KC + q] = sn * x + cs * y;
+            }
+            if (l == 0) *sflag = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int f = *sflag;
+    __syncthreads();
+    if (!f) break;
+  }
+  return sweep + 1;
+}
+
 // T_eps of Us Vs^T (m x K and n x K row-major scratch); on exit the first k
 // columns hold the truncated factors (singular values folded into U).
 // Returns k.
+#define PROF_ADD(slot, v) \
+  do {                     \
+    if (prof && threadIdx.x == 0) atomicAdd(&prof[slot], (unsigned long long)(v)); \
+  } while (0)
+
 template <typename T>
-__device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds& L, int32_t* flags) {
+__device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds& L, int32_t* flags,
+                              unsigned long long* prof = nullptr) {
   const int tid = threadIdx.x;
   if (K == 0) return 0;
+  long long t0 = clock64();
+  PROF_ADD(PS_TRUNC, 1);
+  PROF_ADD(PS_KSUM, K);
   gram(Us, m, K, L.S2, L.S1);
   gram(Vs, n, K, L.S0, L.S1);
+  long long t1 = clock64();
+  PROF_ADD(PS_GRAM, t1 - t0);
   // norm balancing of the column pairs: d_j = sqrt(|v_j| / |u_j|)
   if (tid < K) {
-    double nu = L.S2[tid * KC + tid], nv = L.S0[tid * KC + tid];
-    double d = (nu > 0.0 && nv > 0.0 && isfinite(nu) && isfinite(nv)) ? sqrt(sqrt(nv / nu)) : 0.0;
+    const double nu = L.S2[tid * KC + tid], nv = L.S0[tid * KC + tid];
+    const double d = (nu > 0.0 && nv > 0.0 && isfinite(nu) && isfinite(nv)) ? sqrt(sqrt(nv / nu)) : 0.0;
     L.v0[tid] = d;
     if (!isfinite(nu) || !isfinite(nv)) atomicOr(&flags[FL_NONFINITE], 1);
   }
   __syncthreads();
   for (int idx = tid; idx < K * K; idx += TPB) {
-    int i = idx / K, j = idx - i * K;
-    double di = L.v0[i], dj = L.v0[j];
+    const int i = idx / K, j = idx - i * K;
+    const double di = L.v0[i], dj = L.v0[j];
     L.S2[i * KC + j] *= di * dj;
     L.S0[i * KC + j] = (di > 0.0 && dj > 0.0) ? L.S0[i * KC + j] / (di * dj) : 0.0;
-    L.S1[i * KC + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_eig(L.S0, L.S1, K, L.cs, L.pq, &L.ival[0], &L.dval[0]);
-  // eigenvalues of G_V; keep the numerically non-zero ones
-  if (tid == 0) {
-    double lmax = 0.0;
-    for (int i = 0; i < K; ++i) lmax = fmax(lmax, L.S0[i * KC + i]);
-    int kp = 0;
-    for (int i = 0; i < K; ++i)
-      if (lmax > 0.0 && L.S0[i * KC + i] > 1e-15 * lmax) L.keep[kp++] = i;
-    L.ival[1] = kp;
-  }
-  __syncthreads();
-  const int Kp = L.ival[1];
-  if (Kp == 0) return 0;
-  // L = Q_keep diag(sqrt(lambda)) -> S3 (K x Kp); v1 = lambda_keep
-  for (int idx = tid; idx < K * Kp; idx += TPB) {
-    int i = idx / Kp, a = idx - i * Kp;
-    int ka = L.keep[a];
-    double lam = L.S0[ka * KC + ka];
-    L.S3[i * KC + a] = L.S1[i * KC + ka] * sqrt(lam);
-    if (i == 0) L.v1[a] = lam;
-  }
-  __syncthreads();
-  // temp = G_U L -> S1
-  for (int idx = tid; idx < K * Kp; idx += TPB) {
-    int i = idx / Kp, a = idx - i * Kp;
+  const int rU = pivoted_cholesky(L.S2, K, L.permU, L.posU, L.ival, L.dval, 1e-16);
+  const int rV = pivoted_cholesky(L.S0, K, L.permV, L.posV, L.ival, L.dval, 1e-16);
+  long long t2 = clock64();
+  PROF_ADD(PS_EIG1, t2 - t1);
+  if (rU == 0 || rV == 0) return 0;
+  // core C = R_U P_U^T P_V R_V^T (rU x rV) -> S1 ; Z = I -> S3
+  for (int idx = tid; idx < rU * rV; idx += TPB) {
+    const int a = idx / rV, c = idx - a * rV;
     double s = 0.0;
-    for (int j = 0; j < K; ++j) s += L.S2[i * KC + j] * L.S3[j * KC + a];
-    L.S1[i * KC + a] = s;
-  }
-  __syncthreads();
-  // M = L^T temp -> S0 (Kp x Kp, symmetrised)
-  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
-    int a = idx / Kp, c = idx - a * Kp;
-    double s = 0.0;
-    for (int i = 0; i < K; ++i) s += L.S3[i * KC + a] * L.S1[i * KC + c];
-    L.S0[a * KC + c] = s;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
-    int a = idx / Kp, c = idx - a * Kp;
-    if (a < c) {
-      double s = 0.5 * (L.S0[a * KC + c] + L.S0[c * KC + a]);
-      L.S0[a * KC + c] = s;
-      L.S0[c * KC + a] = s;
+    for (int j = 0; j < K; ++j) {
+      const int pu = L.posU[j], pv = L.posV[j];
+      if (pu >= a && pv >= c) s += L.S2[a * KC + pu] * L.S0[c * KC + pv];
     }
+    L.S1[a * KC + c] = s;
   }
-  for (int idx = tid; idx < Kp * Kp; idx += TPB) {
-    int a = idx / Kp, c = idx - a * Kp;
-    L.S1[a * KC + c] = (a == c) ? 1.0 : 0.0;
+  for (int idx = tid; idx < rV * rV; idx += TPB) {
+    const int a = idx / rV, c = idx - a * rV;
+    L.S3[a * KC + c] = (a == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_eig(L.S0, L.S1, Kp, L.cs, L.pq, &L.ival[0], &L.dval[0]);
-  // singular values, descending order, truncation rank
-  if (tid < Kp) L.v2[tid] = sqrt(fmax(L.S0[tid * KC + tid], 0.0));
+  const int sweeps = onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
+  PROF_ADD(PS_SWEEPS, sweeps);
+  // singular values = column norms of the rotated core; order, rank
+  if (tid < rV) {
+    double s = 0.0;
+    for (int i = 0; i < rU; ++i) s += L.S1[i * KC + tid] * L.S1[i * KC + tid];
+    L.v1[tid] = sqrt(s);
+  }
   __syncthreads();
-  if (tid < Kp) {
-    double sa = L.v2[tid];
+  if (tid < rV) {
+    const double sa = L.v1[tid];
     int rnk = 0;
-    for (int b = 0; b < Kp; ++b) {
-      double sb = L.v2[b];
-      if (sb > sa || (sb == sa && b < tid)) ++rnk;
+    for (int b2 = 0; b2 < rV; ++b2) {
+      const double sb = L.v1[b2];
+      if (sb > sa || (sb == sa && b2 < tid)) ++rnk;
     }
     L.order[rnk] = tid;
   }
   __syncthreads();
   if (tid == 0) {
-    double s1 = L.v2[L.order[0]];
+    const double s1 = L.v1[L.order[0]];
     int k = 0;
     if (s1 > 0.0 && isfinite(s1))
-      while (k < Kp && L.v2[L.order[k]] > eps * s1) ++k;
+      while (k < rV && L.v1[L.order[k]] > eps * s1) ++k;
     if (!isfinite(s1)) atomicOr(&flags[FL_NONFINITE], 1);
     L.ival[2] = k;
   }
   __syncthreads();
   const int k = L.ival[2];
   if (k == 0) return 0;
-  // R_U = diag(d) L W_k -> S2 ;  R_V = diag(1/d) L diag(1/lambda) W_k -> S0
-  // (S0 is overwritten column by column after W is read from S1; the
-  //  eigenvalues are already in v2)
-  for (int idx = tid; idx < K * k; idx += TPB) {
-    int i = idx / k, c = idx - i * k;
-    int w = L.order[c];
-    double su = 0.0, sv = 0.0;
-    for (int a = 0; a < Kp; ++a) {
-      double la = L.S3[i * KC + a] * L.S1[a * KC + w];
-      su += la;
-      sv += la / L.v1[a];
+  // back substitution R_U11 y = C[:, order[c]] and R_V11 y = Z[:, order[c]],
+  // in place, one thread per column
+  if (tid < k) {
+    const int c = L.order[tid];
+    for (int a = rU - 1; a >= 0; --a) {
+      double s = L.S1[a * KC + c];
+      for (int b2 = a + 1; b2 < rU; ++b2) s -= L.S2[a * KC + b2] * L.S1[b2 * KC + c];
+      L.S1[a * KC + c] = s / L.S2[a * KC + a];
     }
-    double d = L.v0[i];
-    L.S2[i * KC + c] = su * d;
-    L.S0[i * KC + c] = (d > 0.0) ? sv / d : 0.0;
+  } else if (tid >= 64 && tid < 64 + k) {
+    const int c = L.order[tid - 64];
+    for (int a = rV - 1; a >= 0; --a) {
+      double s = L.S3[a * KC + c];
+      for (int b2 = a + 1; b2 < rV; ++b2) s -= L.S0[a * KC + b2] * L.S3[b2 * KC + c];
+      L.S3[a * KC + c] = s / L.S0[a * KC + a];
+    }
   }
   __syncthreads();
+  // coefficient matrices in the original column order (balancing included):
+  // X_U -> S2, X_V -> S0
+  for (int idx = tid; idx < K * k; idx += TPB) {
+    const int j = idx / k, c = idx - j * k;
+    const int pu = L.posU[j], pv = L.posV[j];
+    const double d = L.v0[j];
+    const int oc = L.order[c];
+    L.S2[j * KC + c] = (pu < rU) ? d * L.S1[pu * KC + oc] : 0.0;
+    L.S0[j * KC + c] = (pv < rV && d > 0.0) ? L.S3[pv * KC + oc] / d : 0.0;
+  }
+  __syncthreads();
+  long long t3 = clock64();
+  PROF_ADD(PS_EIG2, t3 - t2);
   rebuild(Us, m, K, k, L.S2, L.S1);
   rebuild(Vs, n, K, k, L.S0, L.S1);
+  PROF_ADD(PS_REBUILD, clock64() - t3);
   return k;
 }
 
@@ -618,6 +658,10 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
     const DLeaf tc = A.leaves[tg.cleaf];
     T* C = leaf_base(A, ci, tg.cleaf);
     T* Vs = Us + (int64_t)tc.m * KC;
+    unsigned long long* prof = A.prof;
+    PROF_ADD(PS_ITEMS, 1);
+    PROF_ADD(PS_NPIECES, tg.p1 - tg.p0);
+    const long long tdense0 = clock64();
     if (tc.fmt == 0) {
       // ---------------- dense target
       if (!tg.beta)
@@ -668,6 +712,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           }
         }
       }
+      PROF_ADD(PS_DENSE, clock64() - tdense0);
       continue;
     }
     // ---------------- low-rank target
@@ -719,20 +764,22 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
       while (j0 < w) {
         if (K == KC) {
           // intermediate recompression; keep room for the next columns
-          K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags);
+          K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
           if (K > KC - 8) {
             if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
             K = KC - 8;
           }
         }
         int take = imin(w - j0, KC - K);
+        const long long tp0 = clock64();
         piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
+        PROF_ADD(PS_PIECES_LR, clock64() - tp0);
         K += take;
         j0 += take;
       }
     }
     if (tg.p1 > tg.p0 || !tg.beta) {
-      int k = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags);
+      int k = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
       int kw = imin(k, tc.cap);
       if (tid == 0) {
         if (k > tc.cap) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);

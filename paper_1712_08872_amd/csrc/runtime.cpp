@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "runtime.h"
@@ -208,6 +210,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.scratch_stride = scratch_stride;
       a.eps = opt.eps;
       a.flags = d_flags;
+      a.prof = d_prof;
       launch_accum<float>(a, grid, s);
     } else {
       AccumArgs<double> a{};
@@ -228,6 +231,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.scratch_stride = scratch_stride;
       a.eps = opt.eps;
       a.flags = d_flags;
+      a.prof = d_prof;
       launch_accum<double>(a, grid, s);
     }
   }
@@ -257,6 +261,10 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
   const int64_t M = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
   d_flags = dnew<int32_t>(FL_COUNT);
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
+    d_prof = dnew<unsigned long long>(PS_COUNT);
+    HIPCHK(hipMemsetAsync(d_prof, 0, PS_COUNT * sizeof(unsigned long long), s));
+  }
   // ---- operator
   S = dnew<double>(7 * N);
   if (kind == ACR_STENCIL7_RAW) {
@@ -325,6 +333,15 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   compute_stats();
+  if (d_prof) {
+    unsigned long long pc[PS_COUNT];
+    HIPCHK(hipMemcpy(pc, d_prof, sizeof(pc), hipMemcpyDeviceToHost));
+    const char* names[] = {"pieces_lr", "gram", "eig1", "eig2", "rebuild", "dense", "items", "trunc", "sweeps",
+                           "npieces", "ksum"};
+    fprintf(stderr, "[acr profile]");
+    for (int i = 0; i <= PS_KSUM; ++i) fprintf(stderr, " %s=%.4g", names[i], (double)pc[i]);
+    fprintf(stderr, "\n");
+  }
 }
 
 void Handle::free_factors() {

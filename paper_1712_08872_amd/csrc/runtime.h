@@ -132,6 +132,7 @@ struct Handle {
   int64_t scratch_stride = 0;
   int scratch_slots = 0;
   int32_t* d_flags = nullptr;
+  unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
   int32_t* d_roles = nullptr;
   int roles_cap = 0;
   const double** d_vecs = nullptr;
