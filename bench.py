@@ -1,0 +1,190 @@
+"""Benchmark: ACR setup + CG solve to a 1e-8 relative residual on the
+127^3 variable-coefficient Poisson workload, mixed precision vs FP64.
+
+One step = the whole hot path on one batch of synthetic input: assembly,
+geometry, level-by-level H-matrix cyclic reduction (setup) and the
+ACR-preconditioned CG solve to ||b - A x|| / ||b|| <= 1e-8.  Inputs are
+resident in HBM before the timed region starts.
+
+Workload (seeded, synthetic): 127^3 interior grid (2,048,383 unknowns),
+kappa piecewise constant on 8^3 sub-cubes with values 10^U(-3,3), f ~
+U(-1,1), eps = 1e-4, eta = 2, leaf size 32.
+
+Timed: W warmup steps then K steps in the headline precision (mixed: FP32
+factors, FP64 leaf inversion / truncation cores / Krylov); then K steps in
+FP64 for the mixed-vs-FP64 speedup.  `value` is the mean mixed-precision
+seconds per step (lower is better).
+
+Also printed (same JSON line):
+  roofline      -- the dominant kernel (H-arithmetic accumulation, ALU
+                   bound): algorithmic FP64 flops per launch / mean launch
+                   duration (HIP events on its stream) vs 78.6 TFLOP/s
+  apply_roofline-- the preconditioner application (HBM bound):
+                   algorithmic bytes per apply / apply time vs 8 TB/s
+  cpu_baseline  -- the CPU FP64 oracle on a bounded sample (same recipe at
+                   23^3, ~20 s), projected to 127^3 by the N log^2 N setup
+                   complexity; rank 0, N=1 only.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+METRIC = "ACR setup+solve secs to 1e-8 resid, 127^3 Poisson; mixed vs FP64 GPU speedup"
+
+
+def _inputs(n, seed_offset=0):
+    import synth
+    k = synth.kappa_subcubes(n, 11 + 2 * seed_offset)
+    f = synth.rhs_uniform(n ** 3, 12 + 2 * seed_offset)
+    return k, f
+
+
+def gpu_step(acr, torch, n, kap, f, precision, eps, rtol):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=kap, eps=eps, eta=2.0, leaf_size=32,
+                      precision=precision)
+    t1 = time.perf_counter()
+    x, info = acr.krylov_solve(h, f, method=acr.CG, rtol=rtol, maxit=500)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = acr.acr_stats(h)
+    return h, x, {"seconds": t2 - t0, "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"],
+                  "relres": info["relres_true"], "stats": st}
+
+
+def apply_roofline(acr, torch, h, f, reps=5):
+    stream = torch.cuda.current_stream()
+    z = torch.empty_like(f)
+    acr.acr_apply(h, f, z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        acr.acr_apply(h, f, z, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    b = acr.acr_stats(h)["bytes_per_apply"]
+    gbs = b / t / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_apply": round(t * 1e3, 3),
+            "bytes_per_apply": b}
+
+
+def cpu_baseline(n_sample=23, n_full=127, eps=1e-4):
+    """The oracle (numpy/scipy FP64, single BLAS thread) on the same recipe
+    at n_sample^3, projected to n_full^3 with the N log^2 N setup cost."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+        cores = 1
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    import numpy as np  # noqa: F401
+    from oracle import assembly, hacr, krylov
+    kap, f = _inputs(n_sample)
+    S = assembly.stencil7("poisson", n_sample, n_sample, n_sample, kappa=kap)
+    A = assembly.to_sparse(S, n_sample, n_sample, n_sample)
+    t0 = time.perf_counter()
+    H = hacr.HACR(S, n_sample, n_sample, n_sample, eps=eps, eta=2.0, leaf=32)
+    x, info = krylov.pcg(lambda v: A @ v, f, H.apply, tol=1e-8)
+    t = time.perf_counter() - t0
+    Ns, Nf = n_sample ** 3, n_full ** 3
+    scale = (Nf * math.log2(Nf) ** 2) / (Ns * math.log2(Ns) ** 2)
+    return {"value": round(t * scale, 1), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle setup+PCG on the same recipe at {n_sample}^3 ({t:.1f} s, {info['iters']} iters), "
+                      f"projected x{scale:.0f} by N log^2 N to {n_full}^3",
+            "sample_seconds": round(t, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--n", type=int, default=127)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the plane-sharded multi-GPU "
+              f"path is not built)", file=sys.stderr)
+        sys.exit(2)
+    os.environ["ACR_KERNEL_TIMING"] = "1"
+    import torch
+    import paper_1712_08872_amd as acr
+    n = args.n
+    kap_np, f_np = _inputs(n)
+    kap = torch.from_numpy(kap_np.reshape(-1)).cuda()
+    f = torch.from_numpy(f_np).cuda()
+    torch.cuda.synchronize()
+    for w in range(args.warmup):
+        h, _, r = gpu_step(acr, torch, n, kap, f, acr.MIXED_FP32, args.eps, args.rtol)
+        del h
+        print(f"[bench] warmup {w}: {r['seconds']:.2f} s", file=sys.stderr, flush=True)
+    mixed, fp64 = [], []
+    last = None
+    for k in range(args.steps):
+        if last is not None:
+            del last
+            last = None
+        h, x, r = gpu_step(acr, torch, n, kap, f, acr.MIXED_FP32, args.eps, args.rtol)
+        mixed.append(r)
+        print(f"[bench] mixed step {k}: {r['seconds']:.2f} s (setup {r['setup_s']:.2f}, solve {r['solve_s']:.3f}, "
+              f"{r['iters']} iters)", file=sys.stderr, flush=True)
+        last = h
+    st = mixed[-1]["stats"]
+    aroof = apply_roofline(acr, torch, last, f)
+    del last
+    if not args.no_fp64:
+        for k in range(args.steps):
+            h, _, r = gpu_step(acr, torch, n, kap, f, acr.FP64, args.eps, args.rtol)
+            fp64.append(r)
+            print(f"[bench] fp64 step {k}: {r['seconds']:.2f} s (setup {r['setup_s']:.2f}, "
+                  f"solve {r['solve_s']:.3f}, {r['iters']} iters)", file=sys.stderr, flush=True)
+            del h
+    t_mixed = sum(r["seconds"] for r in mixed) / len(mixed)
+    t_fp64 = sum(r["seconds"] for r in fp64) / len(fp64) if fp64 else None
+    # dominant kernel: H-arithmetic accumulation (ALU bound)
+    launches = max(st["accum_launches"], 1)
+    per_launch_s = st["accum_seconds"] / launches
+    per_launch_flops = st["accum_flops"] / launches
+    tf = per_launch_flops / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
+    roof = {"bound": "alu", "achieved": round(tf, 4), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None, "kernel": "accum_kernel",
+            "launches": st["accum_launches"], "mean_launch_ms": round(per_launch_s * 1e3, 4),
+            "flops_per_launch": per_launch_flops}
+    out = {"metric": METRIC, "value": round(t_mixed, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3, 1), "higher_is_better": False,
+           "scaling": "strong", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+           "config": {"workload": f"variable-coefficient Poisson {n}^3, 8^3 sub-cube kappa 10^U(-3,3), "
+                                  f"eps={args.eps:g}, eta=2, leaf 32, CG to {args.rtol:g}",
+                      "n": n, "unknowns": n ** 3, "precision": "mixed FP32 factors / FP64 Krylov"},
+           "mixed_s": round(t_mixed, 3), "fp64_s": round(t_fp64, 3) if t_fp64 else None,
+           "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3) if t_fp64 else None,
+           "mixed_setup_s": round(mixed[-1]["setup_s"], 3), "mixed_solve_s": round(mixed[-1]["solve_s"], 4),
+           "mixed_iters": mixed[-1]["iters"], "mixed_relres": mixed[-1]["relres"],
+           "fp64_setup_s": round(fp64[-1]["setup_s"], 3) if fp64 else None,
+           "fp64_solve_s": round(fp64[-1]["solve_s"], 4) if fp64 else None,
+           "fp64_iters": fp64[-1]["iters"] if fp64 else None,
+           "max_rank": st["max_rank_all"], "factor_GB": round(st["bytes_factors"] / 1e9, 2),
+           "roofline": roof, "apply_roofline": aroof}
+    if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
+        out["cpu_baseline"] = cpu_baseline(eps=args.eps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

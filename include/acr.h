@@ -125,6 +125,12 @@ typedef struct {
     double setup_seconds;
     double setup_flops;                    /* algorithmic flops counted in setup */
     int32_t precision;
+    /* with the environment variable ACR_KERNEL_TIMING=1 at setup time: the
+       H-arithmetic accumulation kernel's launch count, summed launch
+       durations (HIP events on the launch stream) and algorithmic flops */
+    int32_t accum_launches;
+    double accum_seconds;
+    double accum_flops;
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

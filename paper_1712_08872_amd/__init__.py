@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("max_rank", ctypes.c_int32 * MAX_LEVELS), ("mean_rank", ctypes.c_double * MAX_LEVELS),
                 ("max_rank_all", ctypes.c_int32), ("bytes_factors", ctypes.c_double),
                 ("bytes_allocated", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
-                ("setup_seconds", ctypes.c_double), ("setup_flops", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("setup_seconds", ctypes.c_double), ("setup_flops", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("accum_launches", ctypes.c_int32), ("accum_seconds", ctypes.c_double),
+                ("accum_flops", ctypes.c_double)]
 
     def as_dict(self):
         lv = self.levels
@@ -69,7 +71,9 @@ class Stats(ctypes.Structure):
                 "max_rank": list(self.max_rank[:lv]), "mean_rank": list(self.mean_rank[:lv]),
                 "max_rank_all": self.max_rank_all, "bytes_factors": self.bytes_factors,
                 "bytes_allocated": self.bytes_allocated, "bytes_per_apply": self.bytes_per_apply,
-                "setup_seconds": self.setup_seconds, "precision": self.precision}
+                "setup_seconds": self.setup_seconds, "setup_flops": self.setup_flops, "precision": self.precision,
+                "accum_launches": self.accum_launches, "accum_seconds": self.accum_seconds,
+                "accum_flops": self.accum_flops}
 
 
 SYMBOLS = ["acr_setup", "acr_apply", "acr_apply_T", "acr_matvec", "acr_get_stencil", "krylov_solve",
@@ -154,7 +158,10 @@ class Handle:
 
     def close(self):
         if getattr(self, "ptr", None):
-            lib().acr_destroy(self.ptr)
+            try:
+                lib().acr_destroy(self.ptr)
+            except Exception:  # interpreter shutdown: module globals already cleared
+                pass
             self.ptr = None
 
 

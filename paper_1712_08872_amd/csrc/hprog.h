@@ -75,6 +75,7 @@ struct AccumArgs {
   double eps;
   int32_t* flags;
   unsigned long long* prof;    // optional cycle counters (null = off)
+  double* flops;               // optional algorithmic flop counter (null = off)
 };
 
 // cycle-counter slots of the accumulation kernel

@@ -58,7 +58,13 @@ struct Lds {
   int permU[KC], permV[KC], posU[KC], posV[KC], order[KC];
   int ival[8];
   double dval[4];
+  double flops;          // algorithmic flops of the current item (thread 0)
 };
+
+#define FLOP(L_, x_)                        \
+  do {                                      \
+    if (threadIdx.x == 0) (L_).flops += (double)(x_); \
+  } while (0)
 
 // Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
 // matrix with `rows` rows, accumulated in FP64 into G (ld KC).  `tile` is
@@ -261,6 +267,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   PROF_ADD(PS_KSUM, K);
   gram(Us, m, K, L.S2, L.S1);
   gram(Vs, n, K, L.S0, L.S1);
+  FLOP(L, (double)(m + n) * K * (K + 1));
   long long t1 = clock64();
   PROF_ADD(PS_GRAM, t1 - t0);
   // norm balancing of the column pairs: d_j = sqrt(|v_j| / |u_j|)
@@ -280,6 +287,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   __syncthreads();
   const int rU = pivoted_cholesky(L.S2, K, L.permU, L.posU, L.ival, L.dval, 1e-16);
   const int rV = pivoted_cholesky(L.S0, K, L.permV, L.posV, L.ival, L.dval, 1e-16);
+  FLOP(L, (double)K * K * (rU + rV));
   long long t2 = clock64();
   PROF_ADD(PS_EIG1, t2 - t1);
   if (rU == 0 || rV == 0) return 0;
@@ -300,6 +308,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   __syncthreads();
   const int sweeps = onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
   PROF_ADD(PS_SWEEPS, sweeps);
+  FLOP(L, 2.0 * rU * rV * K + (double)sweeps * (rV / 2) * (rV - 1 + (rV & 1)) * (12.0 * rU + 6.0 * rV));
   // singular values = column norms of the rotated core; order, rank
   if (tid < rV) {
     double s = 0.0;
@@ -361,6 +370,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   PROF_ADD(PS_EIG2, t3 - t2);
   rebuild(Us, m, K, k, L.S2, L.S1);
   rebuild(Vs, n, K, k, L.S0, L.S1);
+  FLOP(L, (double)k * (rU * rU + rV * rV) + 2.0 * (m + n) * K * k);
   PROF_ADD(PS_REBUILD, clock64() - t3);
   return k;
 }
@@ -502,6 +512,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           const int nc = imin(KC, cB - c0);
           tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lam.m, lam.m, vx, x.n, nq, nc, take, L.S0, L.S1,
                      L.S2);
+          FLOP(L, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
             T* d = &Vs[(int64_t)(c0 + cc - tc.c0) * KC + K + jj];
@@ -517,6 +528,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         tn_product(Ul + (q0 - lam.r0), lam.m, vx, x.n, nq, kl, take, L.S0, L.S1, L.S2);
         nn_acc(Vl + (cA - lam.c0), lam.n, cB - cA, kl, L.S0, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
                L.S1);
+        FLOP(L, 2.0 * kl * take * (nq + (cB - cA)));
       }
     }
   } else if (P.kind == PK_LRY) {
@@ -554,6 +566,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           __syncthreads();
           nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lam.m, lam.m, rB - rA, nqc, L.S0, take,
                  Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, L.S1);
+          FLOP(L, 2.0 * (rB - rA) * nqc * take);
         }
       } else {
         const int kl = rank_of(A, xi, l);
@@ -563,6 +576,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         tn_product(Vl + (q0 - lam.c0), lam.n, uy, y.m, nq, kl, take, L.S0, L.S1, L.S2);
         nn_acc(Ul + (rA - lam.r0), lam.m, rB - rA, kl, L.S0, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
                L.S1);
+        FLOP(L, 2.0 * kl * take * (nq + (rB - rA)));
       }
     }
   } else if (P.kind == PK_DD) {
@@ -590,6 +604,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       __syncthreads();
       nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, take,
              Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, L.S1);
+      FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * take);
     }
   } else {  // PK_COPY of a low-rank leaf
     const int si = inst_of(A, b, P.xrole);
@@ -650,6 +665,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
   const int tid = threadIdx.x;
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
+  if (tid == 0) L.flops = 0.0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
     const Target tg = A.targets[A.t0 + item % A.nt];
@@ -687,6 +703,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
               __syncthreads();
               nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, nc,
                      C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
+              FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
             }
           }
         } else if (P.kind == PK_COPY) {
@@ -709,6 +726,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
             int take = imin(KC, w - j0);
             piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
             dense_add_outer(C, tc, Us, Vs, take, L);
+            FLOP(L, 2.0 * tc.m * tc.n * take);
           }
         }
       }
@@ -797,6 +815,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
     }
     __syncthreads();
   }
+  if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
 }
 
 // ------------------------------------------------------------ leaf inverse

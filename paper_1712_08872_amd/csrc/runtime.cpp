@@ -59,6 +59,7 @@ void Handle::dfree(void* p) {
 
 Handle::~Handle() {
   if (hres) (void)hipHostFree(hres);
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (auto& o : owned) {
     if (opt.free)
       opt.free(o.first, opt.alloc_ctx);
@@ -211,7 +212,21 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.eps = opt.eps;
       a.flags = d_flags;
       a.prof = d_prof;
+      a.flops = d_flops;
+      if (timing) {
+        while (ev_pool.size() < ev_used + 2) {
+          hipEvent_t e;
+          HIPCHK(hipEventCreate(&e));
+          ev_pool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+      }
       launch_accum<float>(a, grid, s);
+      if (timing) {
+        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
+        ev_used += 2;
+      }
+      ++accum_launches;
     } else {
       AccumArgs<double> a{};
       a.leaves = d_leaves;
@@ -232,7 +247,21 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.eps = opt.eps;
       a.flags = d_flags;
       a.prof = d_prof;
+      a.flops = d_flops;
+      if (timing) {
+        while (ev_pool.size() < ev_used + 2) {
+          hipEvent_t e;
+          HIPCHK(hipEventCreate(&e));
+          ev_pool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+      }
       launch_accum<double>(a, grid, s);
+      if (timing) {
+        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
+        ev_used += 2;
+      }
+      ++accum_launches;
     }
   }
   HIPCHK(hipGetLastError());
@@ -261,6 +290,11 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
   const int64_t M = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
   d_flags = dnew<int32_t>(FL_COUNT);
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  if (const char* e = getenv("ACR_KERNEL_TIMING"); e && e[0] == '1') {
+    timing = true;
+    d_flops = dnew<double>(1);
+    HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
+  }
   if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
     d_prof = dnew<unsigned long long>(PS_COUNT);
     HIPCHK(hipMemsetAsync(d_prof, 0, PS_COUNT * sizeof(unsigned long long), s));
@@ -326,6 +360,9 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
     }
     // rank capacity exhausted: redo with larger capacities
     free_factors();
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
+    accum_launches = 0;
+    ev_used = 0;
     for (auto& c : caps) c = std::min(KC - 8, std::max(c + 8, (int)(c * 1.5)));
     HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   }
@@ -333,6 +370,18 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   compute_stats();
+  st.accum_launches = accum_launches;
+  if (timing) {
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev_pool[i], ev_pool[i + 1]));
+      ms += t;
+    }
+    st.accum_seconds = ms * 1e-3;
+    HIPCHK(hipMemcpy(&st.accum_flops, d_flops, sizeof(double), hipMemcpyDeviceToHost));
+    st.setup_flops = st.accum_flops;
+  }
   if (d_prof) {
     unsigned long long pc[PS_COUNT];
     HIPCHK(hipMemcpy(pc, d_prof, sizeof(pc), hipMemcpyDeviceToHost));

@@ -133,6 +133,11 @@ struct Handle {
   int scratch_slots = 0;
   int32_t* d_flags = nullptr;
   unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
+  double* d_flops = nullptr;             // optional algorithmic flop counter (ACR_KERNEL_TIMING=1)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  int accum_launches = 0;
   int32_t* d_roles = nullptr;
   int roles_cap = 0;
   const double** d_vecs = nullptr;
