@@ -9,8 +9,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libacr.so")
-SOURCES = ["k_harith.hip", "k_apply.hip", "k_vec.hip", "geometry.cpp", "program.cpp", "runtime.cpp",
-           "krylov.cpp", "api.cpp"]
+# (source, extra flags, object name): the accumulation kernel is built for
+# two round widths
+SOURCES = [("k_harith.hip", ["-DKCV=64"], "k_harith_64"), ("k_harith.hip", ["-DKCV=38"], "k_harith_38"),
+           ("k_apply.hip", [], "k_apply"), ("k_vec.hip", [], "k_vec"), ("geometry.cpp", [], "geometry"),
+           ("program.cpp", [], "program"), ("runtime.cpp", [], "runtime"), ("krylov.cpp", [], "krylov"),
+           ("api.cpp", [], "api")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -21,11 +25,10 @@ def build(verbose=False, jobs=None):
     os.makedirs(objdir, exist_ok=True)
     objs = []
     procs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".", "_") + ".o")
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    for src, extra, name in SOURCES:
+        obj = os.path.join(objdir, name + ".o")
+        lang = ["-x", "hip"] if src.endswith(".cpp") else []
+        cmd = [HIPCC] + FLAGS + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)
     failed = []

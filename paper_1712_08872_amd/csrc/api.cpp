@@ -102,7 +102,7 @@ acr_status acr_setup(const acr_problem* p, const acr_options* o, void* stream, a
   if (!finite_pos(o->eta)) return fail(ACR_E_INVALID, "eta must be positive");
   if (o->leaf_size < 4 || o->leaf_size > 64) return fail(ACR_E_INVALID, "leaf_size must lie in [4, 64]");
   if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32) return fail(ACR_E_INVALID, "unknown precision");
-  if (o->max_rank < 0 || o->max_rank > acr::KC - 8) return fail(ACR_E_INVALID, "max_rank must lie in [0, 56]");
+  if (o->max_rank < 0 || o->max_rank > acr::KC_MAX - 8) return fail(ACR_E_INVALID, "max_rank must lie in [0, 56]");
   if (o->dense_work < 0 || o->dense_work > 64) return fail(ACR_E_INVALID, "dense_work must lie in [0, 64]");
   if ((o->alloc == nullptr) != (o->free == nullptr)) return fail(ACR_E_INVALID, "alloc and free come together");
   if (o->flags != 0) return fail(ACR_E_INVALID, "flags must be 0");

@@ -15,7 +15,7 @@
 
 namespace acr {
 
-constexpr int KC = 64;         // max columns of a low-rank accumulation round
+constexpr int KC_MAX = 64;     // widest low-rank accumulation round the kernels support
 constexpr int TPB = 256;       // threads per block of the H-arithmetic kernels
 
 enum PieceKind : int32_t {
@@ -70,7 +70,7 @@ struct AccumArgs {
   const double* const* vec_ptr;  // [nbatch * nvroles] H-order plane vectors
   T* const* inst_base;         // [ninst]
   int32_t* const* inst_rank;   // [ninst] rank arrays (one entry per leaf)
-  T* scratch;                  // per block slot: (max_m + max_n) * KC
+  T* scratch;                  // per block slot: (max_m + max_n) * round width
   int64_t scratch_stride;
   double eps;
   int32_t* flags;

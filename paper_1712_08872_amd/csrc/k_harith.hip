@@ -20,7 +20,19 @@
 
 #include "hprog.h"
 
+// The accumulation kernel is compiled once per round width KCV (the widest
+// low-rank concatenation held in LDS): a narrow round keeps the LDS
+// footprint small enough for several resident blocks per CU.
+#ifndef KCV
+#define KCV 64
+#endif
+#define ACR_CAT2(a, b) a##b
+#define ACR_CAT(a, b) ACR_CAT2(a, b)
+#define KCNS ACR_CAT(kc, KCV)
+
 namespace acr {
+namespace KCNS {
+constexpr int KC = KCV;
 
 // ------------------------------------------------------------ utilities
 template <typename T>
@@ -49,11 +61,14 @@ __device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
   q = ((Kp - 2 - i + r) % M) + 1;
 }
 
+constexpr int ROUND = 32;  // columns appended between recompressions
+constexpr int LDM = KC + 1;  // padded leading dimension of the K x K matrices (no LDS bank conflicts)
+
 struct Lds {
-  double S0[KC * KC];
-  double S1[KC * KC];
-  double S2[KC * KC];
-  double S3[KC * KC];
+  double S0[KC * LDM];
+  double S1[KC * LDM];
+  double S2[KC * LDM];
+  double S3[KC * LDM];
   double v0[KC], v1[KC];
   int permU[KC], permV[KC], posU[KC], posV[KC], order[KC];
   int ival[8];
@@ -72,7 +87,7 @@ struct Lds {
 template <typename T>
 __device__ void gram(const T* X, int rows, int K, double* G, double* tile) {
   const int tid = threadIdx.x;
-  constexpr int PER = KC * KC / TPB;
+  constexpr int PER = (KC * KC + TPB - 1) / TPB;
   double acc[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) acc[e] = 0.0;
@@ -99,7 +114,7 @@ __device__ void gram(const T* X, int rows, int K, double* G, double* tile) {
   for (int e = 0; e < PER; ++e) {
     int idx = tid + e * TPB;
     int i = idx / KC, j = idx - i * KC;
-    if (i < K && j < K) G[i * KC + j] = acc[e];
+    if (i < K && j < K) G[i * LDM + j] = acc[e];
   }
   __syncthreads();
 }
@@ -118,88 +133,110 @@ __device__ void rebuild(T* X, int rows, int K, int k, const double* R, double* t
     for (int idx = tid; idx < nr * k; idx += TPB) {
       int rr = idx / k, c = idx - rr * k;
       double s = 0.0;
-      for (int i = 0; i < K; ++i) s += tile[rr * KC + i] * R[i * KC + c];
+      for (int i = 0; i < K; ++i) s += tile[rr * KC + i] * R[i * LDM + c];
       X[(int64_t)(r0 + rr) * KC + c] = (T)s;
     }
     __syncthreads();
   }
 }
 
-// Cholesky factorisation with symmetric pivoting of the K x K symmetric
-// positive semi-definite G (LDS, ld KC), in place: on exit the rows a < r
-// of the upper trapezoid hold R (pivot order), perm[a] is the original
-// index of pivot a, pos[] its inverse.  Stops when the largest remaining
-// diagonal entry is <= rel_tol times the largest initial one; returns r.
-__device__ int pivoted_cholesky(double* G, int K, int* perm, int* pos, int* ival, double* dval, double rel_tol) {
-  const int tid = threadIdx.x;
-  if (tid < K) perm[tid] = tid;
-  if (tid == 0) {
-    double d0 = 0.0;
-    for (int i = 0; i < K; ++i) d0 = fmax(d0, G[i * KC + i]);
-    dval[0] = rel_tol * d0;
-  }
-  __syncthreads();
-  const double tol = dval[0];
+// Ordering point inside one wavefront: the LDS accesses of a wavefront are
+// executed in program order, the fences keep the compiler from moving them
+// across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky factorisation with symmetric pivoting of the K x K (K <= 64)
+// symmetric positive semi-definite G (LDS, ld KC), in place, by ONE
+// wavefront (lane j owns column j): on exit the rows a < r of the upper
+// trapezoid hold R (pivot order), perm[a] is the original index of pivot a,
+// pos[] its inverse.  Stops when the largest remaining diagonal entry is <=
+// rel_tol times the largest initial one; returns r (the same in all lanes).
+__device__ int wave_pivoted_cholesky(double* G, int K, int* perm, int* pos, double rel_tol) {
+  const int lane = threadIdx.x & 63;
+  if (lane < K) perm[lane] = lane;
+  double dm = lane < K ? G[lane * LDM + lane] : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+  const double tol = rel_tol * dm;
+  wave_sync();
   int r = 0;
   for (int a = 0; a < K; ++a) {
-    if (tid == 0) {
-      int p = a;
-      double dm = G[a * KC + a];
-      for (int i = a + 1; i < K; ++i)
-        if (G[i * KC + i] > dm) { dm = G[i * KC + i]; p = i; }
-      ival[0] = p;
-      ival[1] = (dm > tol && dm > 0.0) ? 1 : 0;
-      if (ival[1] && p != a) { int t = perm[a]; perm[a] = perm[p]; perm[p] = t; }
+    double v = (lane >= a && lane < K) ? G[lane * LDM + lane] : -1.0;
+    int idx = lane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o);
+      const int i2 = __shfl_xor(idx, o);
+      if (v2 > v || (v2 == v && i2 < idx)) {
+        v = v2;
+        idx = i2;
+      }
     }
-    __syncthreads();
-    if (!ival[1]) break;
-    const int p = ival[0];
+    if (!(v > tol && v > 0.0)) break;
+    const int p = idx;
     if (p != a) {
-      for (int j = tid; j < K; j += TPB) {
-        double t = G[a * KC + j]; G[a * KC + j] = G[p * KC + j]; G[p * KC + j] = t;
+      if (lane < K) {
+        const double t = G[a * LDM + lane];
+        G[a * LDM + lane] = G[p * LDM + lane];
+        G[p * LDM + lane] = t;
       }
-      __syncthreads();
-      for (int i = tid; i < K; i += TPB) {
-        double t = G[i * KC + a]; G[i * KC + a] = G[i * KC + p]; G[i * KC + p] = t;
+      wave_sync();
+      if (lane < K) {
+        const double t = G[lane * LDM + a];
+        G[lane * LDM + a] = G[lane * LDM + p];
+        G[lane * LDM + p] = t;
       }
-      __syncthreads();
+      if (lane == 0) {
+        const int t = perm[a];
+        perm[a] = perm[p];
+        perm[p] = t;
+      }
+      wave_sync();
     }
-    const double rd = sqrt(G[a * KC + a]);
-    __syncthreads();
-    for (int j = a + tid; j < K; j += TPB) G[a * KC + j] = (j == a) ? rd : G[a * KC + j] / rd;
-    __syncthreads();
-    const int rem = K - a - 1;
-    for (int idx = tid; idx < rem * rem; idx += TPB) {
-      const int i = a + 1 + idx / rem, j = a + 1 + idx % rem;
-      G[i * KC + j] -= G[a * KC + i] * G[a * KC + j];
+    const double rd = sqrt(G[a * LDM + a]);
+    wave_sync();
+    if (lane >= a && lane < K) G[a * LDM + lane] = (lane == a) ? rd : G[a * LDM + lane] / rd;
+    wave_sync();
+    if (lane > a && lane < K) {
+      const double rj = G[a * LDM + lane];
+      for (int i = a + 1; i < K; ++i) G[i * LDM + lane] -= G[a * LDM + i] * rj;
     }
-    __syncthreads();
+    wave_sync();
     r = a + 1;
   }
-  if (tid < K) pos[perm[tid]] = tid;
-  __syncthreads();
+  if (lane < K) pos[perm[lane]] = lane;
+  wave_sync();
   return r;
 }
 
 // One-sided Jacobi (Hestenes) on the columns of C (rows x cols, LDS ld KC):
 // C <- C Z with orthogonal columns, Z accumulated (initialised by the
-// caller).  Pairs of columns are processed in tournament order, one pair per
-// group of 8 lanes, dot products reduced with lane shuffles.
+// caller).  Column pairs in tournament order, one pair per group of 8 lanes
+// (up to 32 pairs per round across the block), dot products reduced with
+// lane shuffles, one barrier per round.  Pairs whose inner product is below
+// 1e-15 of the geometric mean of their norms, or below 1e-18 ||C||_F^2,
+// count as orthogonal.  Returns the number of sweeps.
 __device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sflag, double* dval) {
   const int tid = threadIdx.x;
   if (cols <= 1) return 0;
-  const int Kp = cols + (cols & 1), np = Kp / 2;
-  const int g = tid >> 3, l = tid & 7;
-  // pairs whose inner product is below 1e-18 ||C||_F^2 are orthogonal for
-  // every singular value the truncation can keep
-  if (tid == 0) {
+  if (tid < 64) {
     double f = 0.0;
-    for (int i = 0; i < rows; ++i)
-      for (int j = 0; j < cols; ++j) f += C[i * KC + j] * C[i * KC + j];
-    dval[1] = 1e-18 * f;
+    for (int e = tid; e < rows * cols; e += 64) {
+      const double x = C[(e / cols) * LDM + (e % cols)];
+      f += x * x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
+    if (tid == 0) dval[1] = 1e-18 * f;
   }
   __syncthreads();
   const double cabs = dval[1];
+  const int Kp = cols + (cols & 1), np = Kp / 2;
+  const int g = tid >> 3, l = tid & 7;
   int sweep = 0;
   for (; sweep < 30; ++sweep) {
     if (tid == 0) *sflag = 0;
@@ -208,10 +245,15 @@ __device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sf
       if (g < np) {
         int p, q;
         rr_pair(Kp, r, g, p, q);
-        if (q < cols && p < cols) {
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q < cols) {
           double a = 0.0, b = 0.0, c = 0.0;
           for (int i = l; i < rows; i += 8) {
-            const double x = C[i * KC + p], y = C[i * KC + q];
+            const double x = C[i * LDM + p], y = C[i * LDM + q];
             a += x * x;
             b += y * y;
             c += x * y;
@@ -227,14 +269,14 @@ __device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sf
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
             for (int i = l; i < rows; i += 8) {
-              const double x = C[i * KC + p], y = C[i * KC + q];
-              C[i * KC + p] = cs * x - sn * y;
-              C[i * KC + q] = sn * x + cs * y;
+              const double x = C[i * LDM + p], y = C[i * LDM + q];
+              C[i * LDM + p] = cs * x - sn * y;
+              C[i * LDM + q] = sn * x + cs * y;
             }
             for (int i = l; i < cols; i += 8) {
-              const double x = Z[i * KC + p], y = Z[i * KC + q];
-              Z[i * KC + p] = cs * x - sn * y;
-              Z[i * KC + q] = sn * x + cs * y;
+              const double x = Z[i * LDM + p], y = Z[i * LDM + q];
+              Z[i * LDM + p] = cs * x - sn * y;
+              Z[i * LDM + q] = sn * x + cs * y;
             }
             if (l == 0) *sflag = 1;
           }
@@ -272,7 +314,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   PROF_ADD(PS_GRAM, t1 - t0);
   // norm balancing of the column pairs: d_j = sqrt(|v_j| / |u_j|)
   if (tid < K) {
-    const double nu = L.S2[tid * KC + tid], nv = L.S0[tid * KC + tid];
+    const double nu = L.S2[tid * LDM + tid], nv = L.S0[tid * LDM + tid];
     const double d = (nu > 0.0 && nv > 0.0 && isfinite(nu) && isfinite(nv)) ? sqrt(sqrt(nv / nu)) : 0.0;
     L.v0[tid] = d;
     if (!isfinite(nu) || !isfinite(nv)) atomicOr(&flags[FL_NONFINITE], 1);
@@ -281,12 +323,20 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   for (int idx = tid; idx < K * K; idx += TPB) {
     const int i = idx / K, j = idx - i * K;
     const double di = L.v0[i], dj = L.v0[j];
-    L.S2[i * KC + j] *= di * dj;
-    L.S0[i * KC + j] = (di > 0.0 && dj > 0.0) ? L.S0[i * KC + j] / (di * dj) : 0.0;
+    L.S2[i * LDM + j] *= di * dj;
+    L.S0[i * LDM + j] = (di > 0.0 && dj > 0.0) ? L.S0[i * LDM + j] / (di * dj) : 0.0;
   }
   __syncthreads();
-  const int rU = pivoted_cholesky(L.S2, K, L.permU, L.posU, L.ival, L.dval, 1e-16);
-  const int rV = pivoted_cholesky(L.S0, K, L.permV, L.posV, L.ival, L.dval, 1e-16);
+  // the two factorisations run concurrently on waves 0 and 1
+  if (tid < 64) {
+    const int r = wave_pivoted_cholesky(L.S2, K, L.permU, L.posU, 1e-16);
+    if (tid == 0) L.ival[0] = r;
+  } else if (tid < 128) {
+    const int r = wave_pivoted_cholesky(L.S0, K, L.permV, L.posV, 1e-16);
+    if (tid == 64) L.ival[1] = r;
+  }
+  __syncthreads();
+  const int rU = L.ival[0], rV = L.ival[1];
   FLOP(L, (double)K * K * (rU + rV));
   long long t2 = clock64();
   PROF_ADD(PS_EIG1, t2 - t1);
@@ -297,13 +347,13 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     double s = 0.0;
     for (int j = 0; j < K; ++j) {
       const int pu = L.posU[j], pv = L.posV[j];
-      if (pu >= a && pv >= c) s += L.S2[a * KC + pu] * L.S0[c * KC + pv];
+      if (pu >= a && pv >= c) s += L.S2[a * LDM + pu] * L.S0[c * LDM + pv];
     }
-    L.S1[a * KC + c] = s;
+    L.S1[a * LDM + c] = s;
   }
   for (int idx = tid; idx < rV * rV; idx += TPB) {
     const int a = idx / rV, c = idx - a * rV;
-    L.S3[a * KC + c] = (a == c) ? 1.0 : 0.0;
+    L.S3[a * LDM + c] = (a == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int sweeps = onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
@@ -312,7 +362,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   // singular values = column norms of the rotated core; order, rank
   if (tid < rV) {
     double s = 0.0;
-    for (int i = 0; i < rU; ++i) s += L.S1[i * KC + tid] * L.S1[i * KC + tid];
+    for (int i = 0; i < rU; ++i) s += L.S1[i * LDM + tid] * L.S1[i * LDM + tid];
     L.v1[tid] = sqrt(s);
   }
   __syncthreads();
@@ -342,16 +392,16 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   if (tid < k) {
     const int c = L.order[tid];
     for (int a = rU - 1; a >= 0; --a) {
-      double s = L.S1[a * KC + c];
-      for (int b2 = a + 1; b2 < rU; ++b2) s -= L.S2[a * KC + b2] * L.S1[b2 * KC + c];
-      L.S1[a * KC + c] = s / L.S2[a * KC + a];
+      double s = L.S1[a * LDM + c];
+      for (int b2 = a + 1; b2 < rU; ++b2) s -= L.S2[a * LDM + b2] * L.S1[b2 * LDM + c];
+      L.S1[a * LDM + c] = s / L.S2[a * LDM + a];
     }
   } else if (tid >= 64 && tid < 64 + k) {
     const int c = L.order[tid - 64];
     for (int a = rV - 1; a >= 0; --a) {
-      double s = L.S3[a * KC + c];
-      for (int b2 = a + 1; b2 < rV; ++b2) s -= L.S0[a * KC + b2] * L.S3[b2 * KC + c];
-      L.S3[a * KC + c] = s / L.S0[a * KC + a];
+      double s = L.S3[a * LDM + c];
+      for (int b2 = a + 1; b2 < rV; ++b2) s -= L.S0[a * LDM + b2] * L.S3[b2 * LDM + c];
+      L.S3[a * LDM + c] = s / L.S0[a * LDM + a];
     }
   }
   __syncthreads();
@@ -362,8 +412,8 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     const int pu = L.posU[j], pv = L.posV[j];
     const double d = L.v0[j];
     const int oc = L.order[c];
-    L.S2[j * KC + c] = (pu < rU) ? d * L.S1[pu * KC + oc] : 0.0;
-    L.S0[j * KC + c] = (pv < rV && d > 0.0) ? L.S3[pv * KC + oc] / d : 0.0;
+    L.S2[j * LDM + c] = (pu < rU) ? d * L.S1[pu * LDM + oc] : 0.0;
+    L.S0[j * LDM + c] = (pv < rV && d > 0.0) ? L.S3[pv * LDM + oc] / d : 0.0;
   }
   __syncthreads();
   long long t3 = clock64();
@@ -408,7 +458,7 @@ template <typename T>
 __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no, double* Out,
                            double* bP, double* bR) {
   const int tid = threadIdx.x;
-  constexpr int PER = KC * KC / TPB;
+  constexpr int PER = (KC * KC + TPB - 1) / TPB;
   double acc[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) acc[e] = 0.0;
@@ -762,6 +812,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
       continue;
     }
     int K = 0;
+    int kbase = 0;  // rank after the last recompression
     if (tg.beta) {
       const int k0 = *rk;
       for (int idx = tid; idx < tc.m * k0; idx += TPB) {
@@ -773,6 +824,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
         Vs[(int64_t)c * KC + j] = Vc[idx];
       }
       K = k0;
+      kbase = k0;
       __syncthreads();
     }
     for (int p = tg.p0; p < tg.p1; ++p) {
@@ -780,15 +832,18 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
       const int w = piece_width(A, b, P);
       int j0 = 0;
       while (j0 < w) {
-        if (K == KC) {
-          // intermediate recompression; keep room for the next columns
+        // recompress once ROUND columns have been appended beyond the current
+        // rank (the cost of a recompression grows with the cube of its width)
+        const int klim = imin(KC, kbase + ROUND);
+        if (K >= klim) {
           K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
           if (K > KC - 8) {
             if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
             K = KC - 8;
           }
+          kbase = K;
         }
-        int take = imin(w - j0, KC - K);
+        int take = imin(w - j0, imin(KC, kbase + ROUND) - K);
         const long long tp0 = clock64();
         piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
         PROF_ADD(PS_PIECES_LR, clock64() - tp0);
@@ -818,6 +873,17 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
   if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
 }
 
+// ------------------------------------------------------------ launchers
+template <typename T>
+void launch_accum(const AccumArgs<T>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(accum_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
+}
+template void launch_accum<double>(const AccumArgs<double>&, int, hipStream_t);
+template void launch_accum<float>(const AccumArgs<float>&, int, hipStream_t);
+
+}  // namespace KCNS
+
+#if KCV == 64
 // ------------------------------------------------------------ leaf inverse
 // In-place inverse of dense diagonal leaves by Gauss-Jordan elimination with
 // partial pivoting in FP64 (one block per instance).
@@ -925,11 +991,6 @@ __global__ void zcoupling_kernel(const double* S, int64_t N, int B, int nz, cons
   }
 }
 
-// ------------------------------------------------------------ launchers
-template <typename T>
-void launch_accum(const AccumArgs<T>& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(accum_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
-}
 template <typename T>
 void launch_leaf_inverse(T* const* base, const int32_t* insts, int stride, int ninst, int64_t off, int m,
                          int32_t* flags, hipStream_t s) {
@@ -951,9 +1012,6 @@ void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* 
   if (grid > 65535) grid = 65535;
   hipLaunchKernelGGL(zcoupling_kernel, dim3(grid), dim3(256), 0, s, S, N, B, nz, perm, outA, outC);
 }
-
-template void launch_accum<double>(const AccumArgs<double>&, int, hipStream_t);
-template void launch_accum<float>(const AccumArgs<float>&, int, hipStream_t);
 template void launch_leaf_inverse<double>(double* const*, const int32_t*, int, int, int64_t, int, int32_t*,
                                           hipStream_t);
 template void launch_leaf_inverse<float>(float* const*, const int32_t*, int, int, int64_t, int, int32_t*, hipStream_t);
@@ -961,5 +1019,6 @@ template void launch_level0<double>(double* const*, const int32_t*, int, int, co
                                     const int32_t*, const int64_t*, hipStream_t);
 template void launch_level0<float>(float* const*, const int32_t*, int, int, const double*, int64_t, int,
                                    const int32_t*, const int64_t*, hipStream_t);
+#endif
 
 }  // namespace acr

@@ -221,7 +221,10 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
         }
         HIPCHK(hipEventRecord(ev_pool[ev_used], s));
       }
-      launch_accum<float>(a, grid, s);
+      if (kc == 38)
+        kc38::launch_accum<float>(a, grid, s);
+      else
+        kc64::launch_accum<float>(a, grid, s);
       if (timing) {
         HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
         ev_used += 2;
@@ -256,7 +259,10 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
         }
         HIPCHK(hipEventRecord(ev_pool[ev_used], s));
       }
-      launch_accum<double>(a, grid, s);
+      if (kc == 38)
+        kc38::launch_accum<double>(a, grid, s);
+      else
+        kc64::launch_accum<double>(a, grid, s);
       if (timing) {
         HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
         ev_used += 2;
@@ -270,8 +276,8 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
 // ------------------------------------------------------------ setup
 static std::vector<int> initial_caps(const acr_options& o, int depth) {
   int c = o.max_rank;
-  if (c <= 0) c = (int)std::lround(12.0 + 6.0 * std::log10(1.0 / o.eps));
-  c = std::max(8, std::min(KC - 8, c));
+  if (c <= 0) c = (int)std::lround(6.0 + 6.0 * std::log10(1.0 / o.eps));
+  c = std::max(8, std::min(KC_MAX - 8, c));
   return std::vector<int>(depth + 1, c);
 }
 
@@ -352,7 +358,7 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
     if (hflags[FL_SINGULAR]) throw AcrError(ACR_E_SINGULAR, "exactly singular dense leaf in an H-inverse");
     if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite value during setup");
     int cmax = *std::max_element(caps.begin(), caps.end());
-    if (!hflags[FL_RANK_OVERFLOW] || cmax >= KC - 8 || attempt >= 3) {
+    if (!hflags[FL_RANK_OVERFLOW] || cmax >= KC_MAX - 8 || attempt >= 3) {
       st.max_rank_all = hflags[FL_MAXRANK];
       st.retries = attempt;
       if (hflags[FL_RANK_OVERFLOW]) st.rank_overflow = 1;
@@ -363,7 +369,7 @@ void Handle::setup(const acr_problem* p, hipStream_t s) {
     if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
     accum_launches = 0;
     ev_used = 0;
-    for (auto& c : caps) c = std::min(KC - 8, std::max(c + 8, (int)(c * 1.5)));
+    for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
     HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   }
   build_apply_jobs();
@@ -461,7 +467,9 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
   // accumulation scratch: one slot per resident block
   {
     int mm = std::max(G.max_dense_rows, G.max_lr_dim), nn = std::max(G.max_dense_cols, G.max_lr_dim);
-    int64_t stride = (int64_t)(mm + nn) * KC;
+    // narrow rounds (more resident blocks per CU) when every capacity fits
+    kc = (*std::max_element(caps.begin(), caps.end()) <= 30) ? 38 : 64;
+    int64_t stride = (int64_t)(mm + nn) * kc;
     stride = ((stride + 63) / 64) * 64;
     if (stride > scratch_stride || !scratch) {
       if (scratch) dfree(scratch);

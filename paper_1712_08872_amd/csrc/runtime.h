@@ -28,8 +28,13 @@ struct AcrError : std::runtime_error {
                             std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
 
-// kernel launchers
+// kernel launchers (the accumulation kernel exists for round widths 38 and 64)
+namespace kc38 {
 template <typename T> void launch_accum(const AccumArgs<T>&, int grid, hipStream_t);
+}
+namespace kc64 {
+template <typename T> void launch_accum(const AccumArgs<T>&, int grid, hipStream_t);
+}
 template <typename T>
 void launch_leaf_inverse(T* const*, const int32_t*, int stride, int ninst, int64_t off, int m, int32_t* flags,
                          hipStream_t);
@@ -131,6 +136,7 @@ struct Handle {
   void* scratch = nullptr;
   int64_t scratch_stride = 0;
   int scratch_slots = 0;
+  int kc = 64;                 // round width of the accumulation kernel in use
   int32_t* d_flags = nullptr;
   unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
   double* d_flops = nullptr;             // optional algorithmic flop counter (ACR_KERNEL_TIMING=1)
