@@ -1,0 +1,72 @@
+"""Adjoint gradient through the HIP path: ``ACRSolve`` (forward ACR-CG,
+backward adjoint CG preconditioned by the transposed factors, then the
+gradient stencil kernel) against the oracle's dense FP64 reference gradient
+and against central finite differences (relative error <= 1e-5).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gradient
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_08872_amd as acr  # noqa: E402
+
+
+def _J_and_grad(kap, f, u_obs, n, precision, eps):
+    k = torch.from_numpy(kap.reshape(-1)).cuda().requires_grad_(True)
+    ft = torch.from_numpy(f).cuda()
+    uo = torch.from_numpy(u_obs).cuda()
+    u = acr.ACRSolve.apply(k, ft, (n, n, n), eps, 2.0, precision, 1e-13, 500)
+    J = 0.5 * torch.sum((u - uo) ** 2)
+    J.backward()
+    return float(J), k.grad.detach().cpu().numpy().reshape(kap.shape)
+
+
+def _J(kap, f, u_obs, n, precision, eps):
+    k = torch.from_numpy(kap.reshape(-1)).cuda()
+    u = acr.ACRSolve.apply(k, torch.from_numpy(f).cuda(), (n, n, n), eps, 2.0, precision, 1e-13, 500)
+    return float(0.5 * torch.sum((u - torch.from_numpy(u_obs).cuda()) ** 2))
+
+
+def test_gradient_matches_dense_reference():
+    n = 5
+    kap = synth.kappa_lognormal(n, 31)
+    f = synth.rhs_uniform(n ** 3, 32)
+    u_obs = 0.01 * synth.rhs_uniform(n ** 3, 33)
+    J, g = _J_and_grad(kap, f, u_obs, n, acr.FP64, 1e-8)
+    ref = gradient.dense_reference_gradient(kap, f, u_obs, n)
+    np.testing.assert_allclose(g, ref, rtol=1e-8, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gradient_vs_central_differences(precision):
+    n = 11
+    prec = acr.FP64 if precision == "fp64" else acr.MIXED_FP32
+    g0 = synth.gaussian_field_exp((n + 2,) * 3, 41)
+    kap = np.exp(g0)
+    f = synth.rhs_uniform(n ** 3, 42)
+    # observations from a perturbed coefficient plus 1% noise
+    kap2 = np.exp(g0 + 0.25 * synth.gaussian_field_exp((n + 2,) * 3, 43))
+    u2, _ = acr.krylov_solve(acr.acr_setup(n, n, n, acr.POISSON_HARMONIC,
+                                           kappa=torch.from_numpy(kap2.reshape(-1)).cuda(), eps=1e-6),
+                             torch.from_numpy(f).cuda(), rtol=1e-13, maxit=500)
+    u_obs = u2.cpu().numpy() * (1 + 0.01 * np.random.default_rng(44).standard_normal(n ** 3))
+    J0, g = _J_and_grad(kap, f, u_obs, n, prec, 1e-5)
+    rng = np.random.default_rng(45)
+    worst = 0.0
+    for it in range(6):
+        d = rng.standard_normal(kap.shape)
+        d /= np.sqrt(np.mean(d ** 2))
+        an = float(np.sum(g * kap * d))
+        best = np.inf
+        for delta in (1e-3, 1e-4):
+            jp = _J(kap * np.exp(delta * d), f, u_obs, n, prec, 1e-5)
+            jm = _J(kap * np.exp(-delta * d), f, u_obs, n, prec, 1e-5)
+            fd = (jp - jm) / (2 * delta)
+            best = min(best, abs(fd - an) / abs(an))
+        print(f"  direction {it}: relative FD error {best:.2e}")
+        worst = max(worst, best)
+    assert worst <= 1e-5, worst
