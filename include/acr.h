@@ -140,6 +140,25 @@ typedef struct acr_handle acr_handle;
 acr_status acr_setup(const acr_problem* p, const acr_options* o, void* stream,
                      acr_handle** out);
 
+/* Set up `count` independent problems (1 <= count <= 4096) in one handle.
+ * Problems with the same (nx, ny, nz) form a group whose cyclic-reduction
+ * levels run in lockstep: every H-arithmetic step and every apply phase is
+ * one batched launch over all planes of all problems of the group.  Every
+ * vector argument of a batched handle (apply, apply_T, matvec, Krylov,
+ * gradient) is the concatenation of the problems' vectors in the order
+ * given; acr_problem_offset gives the slices.  Problem i's factors equal
+ * those of acr_setup on problem i alone (same arithmetic, same order). */
+acr_status acr_setup_batched(const acr_problem* ps, int32_t count, const acr_options* o, void* stream,
+                             acr_handle** out);
+
+/* Offset and length of problem i's unknowns and of its node grid inside
+ * the concatenated vectors of a (batched) handle.  Any output may be NULL. */
+acr_status acr_problem_offset(const acr_handle* h, int32_t i, int64_t* off, int64_t* n, int64_t* grid_off,
+                              int64_t* grid_n);
+
+/* Number of problems held by a handle (0 for NULL). */
+int32_t acr_num_problems(const acr_handle* h);
+
 /* z = M^{-1} r, forward elimination / top solve / back substitution
  * (Sec. 4.1) with H-matrix-vector products (Sec. 5.3).  r, z: device,
  * N*nrhs doubles, natural ordering, column-major by right-hand side; z

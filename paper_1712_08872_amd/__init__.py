@@ -76,9 +76,9 @@ class Stats(ctypes.Structure):
                 "accum_flops": self.accum_flops}
 
 
-SYMBOLS = ["acr_setup", "acr_apply", "acr_apply_T", "acr_matvec", "acr_get_stencil", "krylov_solve",
-           "acr_grad_kappa", "acr_stats", "acr_destroy", "acr_status_string", "acr_last_error",
-           "acr_default_options"]
+SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",
+           "acr_matvec", "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_destroy",
+           "acr_status_string", "acr_last_error", "acr_default_options"]
 
 _lib = None
 
@@ -96,6 +96,11 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.acr_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    L.acr_setup_batched.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    L.acr_problem_offset.argtypes = [vp, i32, p64, p64, p64, p64]
+    L.acr_num_problems.argtypes = [vp]
+    L.acr_num_problems.restype = i32
     L.acr_apply.argtypes = [vp, vp, vp, i32, vp]
     L.acr_apply_T.argtypes = [vp, vp, vp, i32, vp]
     L.acr_matvec.argtypes = [vp, i32, vp, vp, vp]
@@ -110,8 +115,8 @@ def lib():
     L.acr_last_error.restype = ctypes.c_char_p
     L.acr_default_options.argtypes = [ctypes.POINTER(Options)]
     L.acr_default_options.restype = None
-    for name in ["acr_setup", "acr_apply", "acr_apply_T", "acr_matvec", "acr_get_stencil", "krylov_solve",
-                 "acr_grad_kappa", "acr_stats"]:
+    for name in ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_apply", "acr_apply_T", "acr_matvec",
+                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -146,12 +151,23 @@ def default_options(**kw):
 
 
 class Handle:
-    """Owns an ``acr_handle``; keeps the input tensors alive."""
+    """Owns an ``acr_handle``; keeps the input tensors alive.  ``n`` is the
+    grid of a single-problem handle; ``offsets`` lists (off, N, grid_off,
+    grid_N) per problem; ``total``/``grid_total`` are the concatenated
+    lengths."""
 
     def __init__(self, ptr, n, keep):
         self.ptr = ptr
         self.n = n
         self._keep = keep
+        L = lib()
+        self.offsets = []
+        for i in range(L.acr_num_problems(ptr)):
+            a, b, c, d = (ctypes.c_int64() for _ in range(4))
+            _check(L.acr_problem_offset(ptr, i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+            self.offsets.append((a.value, b.value, c.value, d.value))
+        self.total = sum(o[1] for o in self.offsets)
+        self.grid_total = sum(o[3] for o in self.offsets)
 
     def __del__(self):
         self.close()
@@ -177,10 +193,29 @@ def acr_setup(nx, ny, nz, kind=POISSON_HARMONIC, kappa=None, beta_amp=0.0, beta_
     return Handle(out, (nx, ny, nz), (kappa, c, stencil7))
 
 
+def acr_setup_batched(problems, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64, max_rank=0, dense_work=0,
+                      stream=None):
+    """``acr_setup_batched``: ``problems`` is a list of dicts with the keys of
+    :func:`acr_setup` (nx, ny, nz, kind, kappa, beta_amp, beta_phase, c,
+    omega, stencil7).  Returns one :class:`Handle`."""
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, d in enumerate(problems):
+        arr[i] = Problem(d["nx"], d["ny"], d["nz"], d.get("kind", POISSON_HARMONIC), _ptr(d.get("kappa")),
+                         d.get("beta_amp", 0.0), d.get("beta_phase", 0.0), _ptr(d.get("c")), d.get("omega", 0.0),
+                         _ptr(d.get("stencil7")))
+        keep.append((d.get("kappa"), d.get("c"), d.get("stencil7")))
+    o = default_options(eps=eps, eta=eta, leaf_size=leaf_size, precision=precision, max_rank=max_rank,
+                        dense_work=dense_work)
+    out = ctypes.c_void_p()
+    _check(lib().acr_setup_batched(arr, len(problems), ctypes.byref(o), _stream(stream), ctypes.byref(out)))
+    return Handle(out, None, keep)
+
+
 def acr_apply(h, r, z=None, stream=None):
     import torch
     z = torch.empty_like(r) if z is None else z
-    nrhs = r.numel() // (h.n[0] * h.n[1] * h.n[2])
+    nrhs = r.numel() // h.total
     _check(lib().acr_apply(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
     return z
 
@@ -188,7 +223,7 @@ def acr_apply(h, r, z=None, stream=None):
 def acr_apply_T(h, r, z=None, stream=None):
     import torch
     z = torch.empty_like(r) if z is None else z
-    nrhs = r.numel() // (h.n[0] * h.n[1] * h.n[2])
+    nrhs = r.numel() // h.total
     _check(lib().acr_apply_T(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
     return z
 
@@ -202,8 +237,7 @@ def acr_matvec(h, x, transpose=False, y=None, stream=None):
 
 def acr_get_stencil(h, stream=None):
     import torch
-    N = h.n[0] * h.n[1] * h.n[2]
-    out = torch.empty(7 * N, dtype=torch.float64, device="cuda")
+    out = torch.empty(7 * h.total, dtype=torch.float64, device="cuda")
     _check(lib().acr_get_stencil(h.ptr, _ptr(out), _stream(stream)))
     return out
 
@@ -225,8 +259,7 @@ def krylov_solve(h, b, x=None, method=CG, restart=30, transpose=False, rtol=1e-8
 
 def acr_grad_kappa(h, u, lam, out=None, stream=None):
     import torch
-    nx, ny, nz = h.n
-    out = torch.empty((nz + 2) * (ny + 2) * (nx + 2), dtype=torch.float64, device="cuda") if out is None else out
+    out = torch.empty(h.grid_total, dtype=torch.float64, device="cuda") if out is None else out
     _check(lib().acr_grad_kappa(h.ptr, _ptr(u), _ptr(lam), _ptr(out), _stream(stream)))
     return out
 

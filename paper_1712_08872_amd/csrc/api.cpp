@@ -1,18 +1,22 @@
 // C ABI of libacr (declared in include/acr.h): argument validation on the
 // host before any device work, error codes and thread-local messages, and
-// the handle lifecycle.
+// the handle lifecycle.  A handle holds one or more groups of problems
+// (problems of a group share the plane shape and run every setup and apply
+// step in the same launches).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 
 #include "runtime.h"
 
 namespace acr {
-acr_status krylov_cg(Handle& h, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
+acr_status krylov_cg(Handle& h, int prob, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
                      acr_solve_info* info, hipStream_t s);
-acr_status krylov_gmres(Handle& h, int m, bool tr, double rtol, int maxit, const double* b, double* x,
+acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int maxit, const double* b, double* x,
                         acr_solve_info* info, hipStream_t s);
 }  // namespace acr
 
@@ -54,6 +58,94 @@ acr_status guard(F&& f) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+acr_status check_problem(const acr_problem* p) {
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(ACR_E_INVALID, "grid sizes must be >= 1");
+  if ((int64_t)p->nx * p->ny > (1 << 26) || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34))
+    return fail(ACR_E_INVALID, "grid too large");
+  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_STENCIL7_RAW) return fail(ACR_E_INVALID, "unknown problem kind");
+  if (p->kind == ACR_STENCIL7_RAW && !p->stencil7) return fail(ACR_E_INVALID, "RAW problem needs stencil7");
+  if (p->kind == ACR_HELMHOLTZ && (!p->c || !std::isfinite(p->omega)))
+    return fail(ACR_E_INVALID, "Helmholtz problem needs c and a finite omega");
+  if (p->kind == ACR_CONVDIFF_UPWIND && (!std::isfinite(p->beta_amp) || !std::isfinite(p->beta_phase)))
+    return fail(ACR_E_INVALID, "convection parameters must be finite");
+  return ACR_OK;
+}
+
+acr_status check_options(const acr_options* o) {
+  if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ACR_E_INVALID, "eps must lie in (0, 1)");
+  if (!finite_pos(o->eta)) return fail(ACR_E_INVALID, "eta must be positive");
+  if (o->leaf_size < 4 || o->leaf_size > 64) return fail(ACR_E_INVALID, "leaf_size must lie in [4, 64]");
+  if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32) return fail(ACR_E_INVALID, "unknown precision");
+  if (o->max_rank < 0 || o->max_rank > acr::KC_MAX - 8) return fail(ACR_E_INVALID, "max_rank must lie in [0, 56]");
+  if (o->dense_work < 0 || o->dense_work > 64) return fail(ACR_E_INVALID, "dense_work must lie in [0, 64]");
+  if ((o->alloc == nullptr) != (o->free == nullptr)) return fail(ACR_E_INVALID, "alloc and free come together");
+  if (o->flags != 0) return fail(ACR_E_INVALID, "flags must be 0");
+  return ACR_OK;
+}
+
+// Set up `count` problems: group them by (nx, ny, nz), one group per shape,
+// in order of first appearance.
+acr_status setup_many(const acr_problem* ps, int count, const acr_options* o, void* stream, acr_handle** out) {
+  acr_handle* h = nullptr;
+  acr_status st = guard([&]() {
+    h = new acr_handle();
+    std::map<std::tuple<int, int, int>, int> gid;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < count; ++i) {
+      auto key = std::make_tuple(ps[i].nx, ps[i].ny, ps[i].nz);
+      auto it = gid.find(key);
+      int g;
+      if (it == gid.end()) {
+        g = (int)members.size();
+        gid[key] = g;
+        members.emplace_back();
+      } else {
+        g = it->second;
+      }
+      h->where.emplace_back(g, (int)members[g].size());
+      members[g].push_back(i);
+    }
+    for (int i = 0; i < count; ++i) {
+      h->off.push_back(h->total);
+      h->grid_off.push_back(h->grid_total);
+      h->total += (int64_t)ps[i].nx * ps[i].ny * ps[i].nz;
+      h->grid_total += (int64_t)(ps[i].nx + 2) * (ps[i].ny + 2) * (ps[i].nz + 2);
+    }
+    for (auto& mem : members) {
+      std::vector<acr_problem> group;
+      for (int i : mem) group.push_back(ps[i]);
+      auto grp = std::make_unique<acr::Handle>();
+      grp->opt = *o;
+      grp->setup(group.data(), (int)group.size(), (hipStream_t)stream);
+      h->groups.push_back(std::move(grp));
+    }
+    return ACR_OK;
+  });
+  if (st != ACR_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return ACR_OK;
+}
+
+// Run f(group, per-problem input pointers, per-problem output pointers) for
+// every group, slicing concatenated vectors at the problem offsets.
+template <typename F>
+void for_groups(acr_handle* h, const double* r, double* z, F&& f) {
+  for (size_t g = 0; g < h->groups.size(); ++g) {
+    acr::Handle& grp = *h->groups[g];
+    std::vector<const double*> in(grp.probs.size());
+    std::vector<double*> outp(grp.probs.size());
+    for (size_t i = 0; i < h->where.size(); ++i)
+      if (h->where[i].first == (int)g) {
+        in[h->where[i].second] = r + h->off[i];
+        outp[h->where[i].second] = z + h->off[i];
+      }
+    f(grp, in, outp);
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -89,37 +181,40 @@ const char* acr_last_error(void) { return g_last_error.c_str(); }
 acr_status acr_setup(const acr_problem* p, const acr_options* o, void* stream, acr_handle** out) {
   if (out) *out = nullptr;
   if (!p || !o || !out) return fail(ACR_E_INVALID, "null argument");
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(ACR_E_INVALID, "grid sizes must be >= 1");
-  if ((int64_t)p->nx * p->ny > (1 << 26) || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34))
-    return fail(ACR_E_INVALID, "grid too large");
-  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_STENCIL7_RAW) return fail(ACR_E_INVALID, "unknown problem kind");
-  if (p->kind == ACR_STENCIL7_RAW && !p->stencil7) return fail(ACR_E_INVALID, "RAW problem needs stencil7");
-  if (p->kind == ACR_HELMHOLTZ && (!p->c || !std::isfinite(p->omega)))
-    return fail(ACR_E_INVALID, "Helmholtz problem needs c and a finite omega");
-  if (p->kind == ACR_CONVDIFF_UPWIND && (!std::isfinite(p->beta_amp) || !std::isfinite(p->beta_phase)))
-    return fail(ACR_E_INVALID, "convection parameters must be finite");
-  if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ACR_E_INVALID, "eps must lie in (0, 1)");
-  if (!finite_pos(o->eta)) return fail(ACR_E_INVALID, "eta must be positive");
-  if (o->leaf_size < 4 || o->leaf_size > 64) return fail(ACR_E_INVALID, "leaf_size must lie in [4, 64]");
-  if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32) return fail(ACR_E_INVALID, "unknown precision");
-  if (o->max_rank < 0 || o->max_rank > acr::KC_MAX - 8) return fail(ACR_E_INVALID, "max_rank must lie in [0, 56]");
-  if (o->dense_work < 0 || o->dense_work > 64) return fail(ACR_E_INVALID, "dense_work must lie in [0, 64]");
-  if ((o->alloc == nullptr) != (o->free == nullptr)) return fail(ACR_E_INVALID, "alloc and free come together");
-  if (o->flags != 0) return fail(ACR_E_INVALID, "flags must be 0");
-  acr_status ds = device_check();
-  if (ds != ACR_OK) return ds;
-  acr_handle* h = nullptr;
-  acr_status st = guard([&]() {
-    h = new acr_handle();
-    h->h.opt = *o;
-    h->h.setup(p, (hipStream_t)stream);
-    return ACR_OK;
-  });
-  if (st != ACR_OK) {
-    delete h;
-    return st;
+  acr_status s = check_problem(p);
+  if (s != ACR_OK) return s;
+  s = check_options(o);
+  if (s != ACR_OK) return s;
+  s = device_check();
+  if (s != ACR_OK) return s;
+  return setup_many(p, 1, o, stream, out);
+}
+
+acr_status acr_setup_batched(const acr_problem* ps, int32_t count, const acr_options* o, void* stream,
+                             acr_handle** out) {
+  if (out) *out = nullptr;
+  if (!ps || !o || !out) return fail(ACR_E_INVALID, "null argument");
+  if (count < 1 || count > 4096) return fail(ACR_E_INVALID, "count must lie in [1, 4096]");
+  for (int i = 0; i < count; ++i) {
+    acr_status s = check_problem(ps + i);
+    if (s != ACR_OK) return fail(s, "problem " + std::to_string(i) + ": " + g_last_error);
   }
-  *out = h;
+  acr_status s = check_options(o);
+  if (s != ACR_OK) return s;
+  s = device_check();
+  if (s != ACR_OK) return s;
+  return setup_many(ps, count, o, stream, out);
+}
+
+acr_status acr_problem_offset(const acr_handle* h, int32_t i, int64_t* off, int64_t* n, int64_t* grid_off,
+                              int64_t* grid_n) {
+  if (!h) return fail(ACR_E_INVALID, "null handle");
+  if (i < 0 || i >= (int)h->where.size()) return fail(ACR_E_INVALID, "problem index out of range");
+  const acr::Handle& g = *h->groups[h->where[i].first];
+  if (off) *off = h->off[i];
+  if (n) *n = g.N;
+  if (grid_off) *grid_off = h->grid_off[i];
+  if (grid_n) *grid_n = (int64_t)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
   return ACR_OK;
 }
 
@@ -128,7 +223,11 @@ acr_status acr_apply(acr_handle* h, const double* r, double* z, int32_t nrhs, vo
   if (nrhs < 1) return fail(ACR_E_INVALID, "nrhs must be >= 1");
   if (r == z) return fail(ACR_E_INVALID, "z must not alias r");
   return guard([&]() {
-    for (int k = 0; k < nrhs; ++k) h->h.apply(r + (int64_t)k * h->h.N, z + (int64_t)k * h->h.N, false, (hipStream_t)stream);
+    for (int k = 0; k < nrhs; ++k)
+      for_groups(h, r + (int64_t)k * h->total, z + (int64_t)k * h->total,
+                 [&](acr::Handle& g, const std::vector<const double*>& in, const std::vector<double*>& outp) {
+                   g.apply(in, outp, false, -1, (hipStream_t)stream);
+                 });
     return ACR_OK;
   });
 }
@@ -138,7 +237,11 @@ acr_status acr_apply_T(acr_handle* h, const double* r, double* z, int32_t nrhs, 
   if (nrhs < 1) return fail(ACR_E_INVALID, "nrhs must be >= 1");
   if (r == z) return fail(ACR_E_INVALID, "z must not alias r");
   return guard([&]() {
-    for (int k = 0; k < nrhs; ++k) h->h.apply(r + (int64_t)k * h->h.N, z + (int64_t)k * h->h.N, true, (hipStream_t)stream);
+    for (int k = 0; k < nrhs; ++k)
+      for_groups(h, r + (int64_t)k * h->total, z + (int64_t)k * h->total,
+                 [&](acr::Handle& g, const std::vector<const double*>& in, const std::vector<double*>& outp) {
+                   g.apply(in, outp, true, -1, (hipStream_t)stream);
+                 });
     return ACR_OK;
   });
 }
@@ -147,7 +250,9 @@ acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double*
   if (!h || !x || !y) return fail(ACR_E_INVALID, "null argument");
   if (x == y) return fail(ACR_E_INVALID, "y must not alias x");
   return guard([&]() {
-    h->h.matvec(x, y, transpose != 0, (hipStream_t)stream);
+    for (size_t i = 0; i < h->where.size(); ++i)
+      h->groups[h->where[i].first]->matvec(h->where[i].second, x + h->off[i], y + h->off[i], transpose != 0,
+                                           (hipStream_t)stream);
     return ACR_OK;
   });
 }
@@ -155,7 +260,11 @@ acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double*
 acr_status acr_get_stencil(acr_handle* h, double* out, void* stream) {
   if (!h || !out) return fail(ACR_E_INVALID, "null argument");
   return guard([&]() {
-    HIPCHK(hipMemcpyAsync(out, h->h.S, 7 * h->h.N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    for (size_t i = 0; i < h->where.size(); ++i) {
+      const acr::Handle& g = *h->groups[h->where[i].first];
+      HIPCHK(hipMemcpyAsync(out + 7 * h->off[i], g.probs[h->where[i].second].S, 7 * g.N * sizeof(double),
+                            hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    }
     return ACR_OK;
   });
 }
@@ -171,10 +280,25 @@ acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t 
   std::memset(info, 0, sizeof(*info));
   acr_status result = ACR_OK;
   acr_status st = guard([&]() {
-    if (method == ACR_GMRES)
-      result = acr::krylov_gmres(h->h, restart, transpose != 0, rtol, maxit, b, x, info, (hipStream_t)stream);
-    else
-      result = acr::krylov_cg(h->h, method == ACR_FCG, transpose != 0, rtol, maxit, b, x, info, (hipStream_t)stream);
+    // each problem is solved to its own tolerance; the info reports the
+    // largest iteration count and residual and the first failure
+    for (size_t i = 0; i < h->where.size(); ++i) {
+      acr::Handle& g = *h->groups[h->where[i].first];
+      const int q = h->where[i].second;
+      acr_solve_info one{};
+      acr_status r;
+      if (method == ACR_GMRES)
+        r = acr::krylov_gmres(g, q, restart, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
+                              (hipStream_t)stream);
+      else
+        r = acr::krylov_cg(g, q, method == ACR_FCG, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
+                           (hipStream_t)stream);
+      info->iters = std::max(info->iters, one.iters);
+      info->relres_true = std::max(info->relres_true, one.relres_true);
+      if (one.variant == ACR_FCG || i == 0) info->variant = one.variant;
+      if (r != ACR_OK && result == ACR_OK) result = r;
+    }
+    info->status = result;
     return ACR_OK;
   });
   if (st != ACR_OK) return st;
@@ -184,10 +308,18 @@ acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t 
 
 acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa, void* stream) {
   if (!h || !u || !lam || !dkappa) return fail(ACR_E_INVALID, "null argument");
-  if (h->h.kind != ACR_POISSON_HARMONIC) return fail(ACR_E_INVALID, "gradient needs a harmonic-average Poisson problem");
-  if (!h->h.kappa) return fail(ACR_E_INVALID, "gradient needs the problem's kappa");
+  for (size_t i = 0; i < h->where.size(); ++i) {
+    const acr::Prob& P = h->groups[h->where[i].first]->probs[h->where[i].second];
+    if (P.kind != ACR_POISSON_HARMONIC) return fail(ACR_E_INVALID, "gradient needs harmonic-average Poisson problems");
+    if (!P.kappa) return fail(ACR_E_INVALID, "gradient needs the problem's kappa");
+  }
   return guard([&]() {
-    acr::launch_grad_kappa(h->h.nx, h->h.ny, h->h.nz, h->h.kappa, u, lam, dkappa, (hipStream_t)stream);
+    for (size_t i = 0; i < h->where.size(); ++i) {
+      const acr::Handle& g = *h->groups[h->where[i].first];
+      const acr::Prob& P = g.probs[h->where[i].second];
+      acr::launch_grad_kappa(g.nx, g.ny, g.nz, P.kappa, u + h->off[i], lam + h->off[i], dkappa + h->grid_off[i],
+                             (hipStream_t)stream);
+    }
     HIPCHK(hipGetLastError());
     return ACR_OK;
   });
@@ -195,10 +327,30 @@ acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, dou
 
 acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
   if (!h || !st) return fail(ACR_E_INVALID, "null argument");
-  *st = h->h.st;
-  st->bytes_allocated = (double)h->h.bytes_alloc;
+  // one group: its statistics; several groups: sums and maxima
+  *st = h->groups[0]->st;
+  st->bytes_allocated = (double)h->groups[0]->bytes_alloc;
+  for (size_t g = 1; g < h->groups.size(); ++g) {
+    const acr_stats_t& o = h->groups[g]->st;
+    st->factors += o.factors;
+    st->retries = std::max(st->retries, o.retries);
+    st->rank_overflow |= o.rank_overflow;
+    for (int r = 0; r < ACR_MAX_LEVELS; ++r) st->max_rank[r] = std::max(st->max_rank[r], o.max_rank[r]);
+    st->max_rank_all = std::max(st->max_rank_all, o.max_rank_all);
+    st->bytes_factors += o.bytes_factors;
+    st->bytes_allocated += (double)h->groups[g]->bytes_alloc;
+    st->bytes_per_apply += o.bytes_per_apply;
+    st->setup_seconds += o.setup_seconds;
+    st->setup_flops += o.setup_flops;
+    st->accum_launches += o.accum_launches;
+    st->accum_seconds += o.accum_seconds;
+    st->accum_flops += o.accum_flops;
+    st->levels = std::max(st->levels, o.levels);
+  }
   return ACR_OK;
 }
+
+int32_t acr_num_problems(const acr_handle* h) { return h ? (int32_t)h->where.size() : 0; }
 
 void acr_destroy(acr_handle* h) {
   if (!h) return;

@@ -1,0 +1,662 @@
+// Cyclic reduction with H-matrix plane blocks (Sec. 4.1-4.2): setup of one
+// group of problems, the preconditioner sweeps and statistics.
+//
+// Level r on the ordered plane list P_r: the planes at 1-based odd positions
+// are eliminated (E_r), the others kept (K_r).  For i in E_r:
+// Dinv_i = H-inv(D_i).  For kept j with neighbours j-1, j+1:
+// X = A_j Dinv_{j-1}, Y = C_j Dinv_{j+1}, D_j <- D_j - X C_{j-1} - Y A_{j+1},
+// A_j <- -X A_{j-1}, C_j <- -Y C_{j+1} (formatted products with truncation).
+// At level 0 the couplings are the diagonal z-couplings, so X C_{j-1} is a
+// row/column scaling of Dinv_{j-1}.  The level-r couplings are stored before
+// they are updated; the recursion ends with the H-inverse of the last plane.
+//
+// All problems of a group have the same plane shape and plane count, so
+// their levels coincide and every step is one batched launch over all
+// planes of all problems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace acr {
+
+static std::vector<int> initial_caps(const acr_options& o, int depth) {
+  int c = o.max_rank;
+  if (c <= 0) c = (int)std::lround(6.0 + 6.0 * std::log10(1.0 / o.eps));
+  c = std::max(8, std::min(KC_MAX - 8, c));
+  return std::vector<int>(depth + 1, c);
+}
+
+void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
+  auto t_start = std::chrono::steady_clock::now();
+  nx = ps[0].nx;
+  ny = ps[0].ny;
+  nz = ps[0].nz;
+  B = nx * ny;
+  N = (int64_t)B * nz;
+  fp32 = opt.precision == ACR_MIXED_FP32;
+  const int64_t M = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+  d_flags = dnew<int32_t>(FL_COUNT);
+  HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  if (const char* e = getenv("ACR_KERNEL_TIMING"); e && e[0] == '1') {
+    timing = true;
+    d_flops = dnew<double>(1);
+    HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
+  }
+  if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
+    d_prof = dnew<unsigned long long>(PS_COUNT);
+    HIPCHK(hipMemsetAsync(d_prof, 0, PS_COUNT * sizeof(unsigned long long), s));
+  }
+  // ---- operators
+  probs.assign(count, Prob{});
+  for (int q = 0; q < count; ++q) {
+    const acr_problem* p = ps + q;
+    Prob& P = probs[q];
+    P.kind = p->kind;
+    P.beta_amp = p->beta_amp;
+    P.beta_phase = p->beta_phase;
+    P.omega = p->omega;
+    P.S = dnew<double>(7 * N);
+    if (P.kind == ACR_STENCIL7_RAW) {
+      HIPCHK(hipMemcpyAsync(P.S, p->stencil7, 7 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_check(P.S, 7 * N, 0, d_flags + FL_NONFINITE, s);
+    } else {
+      if (p->kappa) {
+        P.kappa = dnew<double>(M);
+        HIPCHK(hipMemcpyAsync(P.kappa, p->kappa, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_check(P.kappa, M, 1, d_flags + FL_NONFINITE, s);
+      }
+      if (P.kind == ACR_HELMHOLTZ) launch_check(p->c, M, 1, d_flags + FL_NONFINITE, s);
+      launch_assemble(P.kind == ACR_CONVDIFF_UPWIND ? 1 : (P.kind == ACR_HELMHOLTZ ? 2 : 0), nx, ny, nz, P.kappa,
+                      P.beta_amp, P.beta_phase, p->c, P.omega, P.S, s);
+      launch_check(P.S, 7 * N, 0, d_flags + FL_NONFINITE, s);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  int32_t hflags[FL_COUNT];
+  HIPCHK(hipMemcpyAsync(hflags, d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite or non-positive coefficient");
+
+  // ---- geometry and its device tables
+  G = build_geometry(nx, ny, opt.leaf_size, opt.eta, opt.dense_work);
+  d_perm = upload(G.perm);
+  {
+    std::vector<int32_t> seg_lo, rp{0}, ri, cp{0}, ci;
+    for (int lc : G.leaf_clusters) seg_lo.push_back(G.cl[lc].lo);
+    seg_lo.push_back(B);
+    for (size_t k = 0; k < G.leaf_clusters.size(); ++k) {
+      for (int l : G.rows_of_seg[k]) ri.push_back(l);
+      rp.push_back((int32_t)ri.size());
+      for (int l : G.cols_of_seg[k]) ci.push_back(l);
+      cp.push_back((int32_t)ci.size());
+    }
+    d_seg_lo = upload(seg_lo);
+    d_rows_ptr = upload(rp);
+    d_rows_idx = upload(ri);
+    d_cols_ptr = upload(cp);
+    d_cols_idx = upload(ci);
+  }
+  for (Prob& P : probs) {
+    P.zA = dnew<double>(N);
+    P.zC = dnew<double>(N);
+    launch_zcoupling(P.S, N, B, nz, d_perm, P.zA, P.zC, s);
+  }
+
+  std::vector<int> caps = initial_caps(opt, G.max_depth());
+  for (int attempt = 0;; ++attempt) {
+    build_factors(s, caps);
+    HIPCHK(hipMemcpyAsync(hflags, d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflags[FL_SINGULAR]) throw AcrError(ACR_E_SINGULAR, "exactly singular dense leaf in an H-inverse");
+    if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite value during setup");
+    int cmax = *std::max_element(caps.begin(), caps.end());
+    if (!hflags[FL_RANK_OVERFLOW] || cmax >= KC_MAX - 8 || attempt >= 3) {
+      st.max_rank_all = hflags[FL_MAXRANK];
+      st.retries = attempt;
+      if (hflags[FL_RANK_OVERFLOW]) st.rank_overflow = 1;
+      break;
+    }
+    // rank capacity exhausted: redo with larger capacities
+    free_factors();
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
+    accum_launches = 0;
+    ev_used = 0;
+    for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
+    HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  }
+  build_apply_jobs();
+  HIPCHK(hipStreamSynchronize(s));
+  const int retries = st.retries, overflow = st.rank_overflow, maxr = st.max_rank_all;
+  compute_stats();
+  st.retries = retries;
+  st.rank_overflow = overflow;
+  st.max_rank_all = maxr;
+  st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  st.accum_launches = accum_launches;
+  if (timing) {
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev_pool[i], ev_pool[i + 1]));
+      ms += t;
+    }
+    st.accum_seconds = ms * 1e-3;
+    HIPCHK(hipMemcpy(&st.accum_flops, d_flops, sizeof(double), hipMemcpyDeviceToHost));
+    st.setup_flops = st.accum_flops;
+  }
+  if (d_prof) {
+    unsigned long long pc[PS_COUNT];
+    HIPCHK(hipMemcpy(pc, d_prof, sizeof(pc), hipMemcpyDeviceToHost));
+    const char* names[] = {"pieces_lr", "gram", "eig1", "eig2", "rebuild", "dense", "items", "trunc", "sweeps",
+                           "npieces", "ksum"};
+    fprintf(stderr, "[acr profile]");
+    for (int i = 0; i <= PS_KSUM; ++i) fprintf(stderr, " %s=%.4g", names[i], (double)pc[i]);
+    fprintf(stderr, "\n");
+  }
+}
+
+void Handle::free_factors() {
+  for (Prob& P : probs) {
+    P.levels.clear();
+    P.top_inst = P.top_plane = -1;
+    P.plane_inst.clear();
+  }
+  for (size_t i = 0; i < inst.size(); ++i)
+    if (inst[i].live) release_instance((int)i);
+}
+
+void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
+  G.assign_caps(caps);
+  // device leaf table (offsets depend on the capacities)
+  {
+    std::vector<DLeaf> dl(G.lf.size());
+    for (size_t i = 0; i < G.lf.size(); ++i) {
+      const Leaf& L = G.lf[i];
+      dl[i] = DLeaf{L.m, L.n, L.r0, L.c0, L.fmt, L.cap, L.off};
+    }
+    if (d_leaves) dfree(d_leaves);
+    d_leaves = upload(dl);
+    std::vector<int32_t> lrl;
+    std::vector<int64_t> soff(G.lf.size(), 0);
+    int64_t acc = 0;
+    for (size_t i = 0; i < G.lf.size(); ++i)
+      if (G.lf[i].fmt == LF_LR) {
+        lrl.push_back((int32_t)i);
+        soff[i] = acc;
+        acc += G.lf[i].cap;
+      }
+    sstride = std::max<int64_t>(acc, 1);
+    if (d_lr_leaves) dfree(d_lr_leaves);
+    if (d_soff) dfree(d_soff);
+    d_lr_leaves = upload(lrl);
+    d_soff = upload(soff);
+    // level-0 scatter map: in-plane couplings -> dense leaf entries
+    std::vector<int64_t> map(5 * (size_t)B, -1);
+    std::vector<int> pos(B);
+    for (int i = 0; i < B; ++i) pos[G.perm[i]] = i;
+    auto find_leaf = [&](int i, int j) {
+      int nd = 0;
+      while (G.bn[nd].kind == BK_H) {
+        const BNode& b = G.bn[nd];
+        int ii = i < G.cl[G.cl[b.t].c0].hi ? 0 : 1;
+        int jj = j < G.cl[G.cl[b.s].c0].hi ? 0 : 1;
+        nd = b.ch[2 * ii + jj];
+      }
+      return G.bn[nd].leaf;
+    };
+    const int dxs[5] = {0, -1, 1, 0, 0}, dys[5] = {0, 0, 0, -1, 1};
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        int i = pos[x + nx * y];
+        for (int d = 0; d < 5; ++d) {
+          int xx = x + dxs[d], yy = y + dys[d];
+          if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) continue;
+          int j = pos[xx + nx * yy];
+          int l = find_leaf(i, j);
+          const Leaf& L = G.lf[l];
+          if (L.fmt != LF_DENSE) throw AcrError(ACR_E_INVALID, "level-0 coupling in a low-rank leaf");
+          map[(size_t)d * B + i] = L.off + (i - L.r0) + (int64_t)(j - L.c0) * L.m;
+        }
+      }
+    if (d_l0map) dfree(d_l0map);
+    d_l0map = upload(map);
+  }
+  get_program("inv");
+  // accumulation scratch: one slot per resident block
+  {
+    int mm = std::max(G.max_dense_rows, G.max_lr_dim), nn = std::max(G.max_dense_cols, G.max_lr_dim);
+    // narrow rounds (more resident blocks per CU) when every capacity fits
+    kc = (*std::max_element(caps.begin(), caps.end()) <= 30) ? 38 : 64;
+    int64_t stride = (int64_t)(mm + nn) * kc;
+    stride = ((stride + 63) / 64) * 64;
+    if (stride > scratch_stride || !scratch) {
+      if (scratch) dfree(scratch);
+      scratch_slots = 2048;
+      scratch_stride = stride;
+      scratch = dmalloc((size_t)scratch_slots * stride * (fp32 ? 4 : 8));
+    }
+  }
+
+  // ---- level 0: the plane operators D_k as H-matrices
+  const int np = (int)probs.size();
+  for (Prob& P : probs) {
+    P.plane_inst.assign(nz, -1);
+    for (int k = 0; k < nz; ++k) P.plane_inst[k] = new_instance(s);
+  }
+  sync_tables();
+  for (Prob& P : probs) {
+    int32_t* d_pi = upload(P.plane_inst);
+    if (fp32)
+      launch_level0<float>((float* const*)d_inst_base, d_pi, nz, 0, P.S, N, B, d_perm, d_l0map, s);
+    else
+      launch_level0<double>((double* const*)d_inst_base, d_pi, nz, 0, P.S, N, B, d_perm, d_l0map, s);
+    HIPCHK(hipStreamSynchronize(s));
+    dfree(d_pi);
+  }
+  std::vector<std::vector<Coupling>> Acur(np, std::vector<Coupling>(nz)), Ccur(np, std::vector<Coupling>(nz));
+  for (int q = 0; q < np; ++q)
+    for (int k = 0; k < nz; ++k) {
+      if (k > 0) Acur[q][k] = Coupling{1, -1, probs[q].zA + (int64_t)k * B};
+      if (k < nz - 1) Ccur[q][k] = Coupling{1, -1, probs[q].zC + (int64_t)k * B};
+    }
+  // scratch instances of the H-inverse
+  std::vector<int> tpool;
+  auto inverse_batch = [&](const std::vector<int>& planes) {
+    const size_t nb = planes.size() * np;
+    while (tpool.size() < nb) tpool.push_back(new_instance(s));
+    std::vector<int32_t> roles;
+    size_t b = 0;
+    for (int q = 0; q < np; ++q)
+      for (int pl : planes) {
+        roles.push_back(probs[q].plane_inst[pl]);
+        roles.push_back(tpool[b++]);
+      }
+    run_program(get_program("inv"), (int)nb, 2, roles, 0, {}, s);
+  };
+
+  std::vector<int> P(nz);
+  for (int k = 0; k < nz; ++k) P[k] = k;
+  int lev = 0;
+  while (true) {
+    if (P.size() == 1) {
+      inverse_batch(P);
+      for (Prob& pr : probs) {
+        pr.top_plane = P[0];
+        pr.top_inst = pr.plane_inst[P[0]];
+      }
+      break;
+    }
+    Level L;
+    L.P = P;
+    for (size_t q = 0; q < P.size(); ++q) (q % 2 == 0 ? L.E : L.K).push_back(P[q]);
+    inverse_batch(L.E);
+    std::vector<std::vector<Coupling>> An(np, std::vector<Coupling>(nz)), Cn(np, std::vector<Coupling>(nz));
+    for (int q = 0; q < np; ++q) {
+      Level Lq = L;
+      for (int i : L.E) Lq.dinv[i] = probs[q].plane_inst[i];
+      for (int p : P) {
+        Lq.A[p] = Acur[q][p];
+        Lq.C[p] = Ccur[q][p];
+      }
+      probs[q].levels.push_back(Lq);
+    }
+    if (lev == 0) {
+      // D_j <- D_j - diag(a_j) Dinv_{j-1} diag(c_{j-1}) - diag(c_j) Dinv_{j+1} diag(a_{j+1})
+      std::vector<int32_t> roles, roles2;
+      std::vector<const double*> vecs, vecs2;
+      for (int q = 0; q < np; ++q) {
+        const auto& pi = probs[q].plane_inst;
+        for (size_t m = 0; m < L.K.size(); ++m) {
+          const int pos = 2 * (int)m + 1;
+          const int j = P[pos], im = P[pos - 1];
+          const int ip = pos + 1 < (int)P.size() ? P[pos + 1] : -1;
+          roles.push_back(pi[j]);
+          roles.push_back(pi[im]);
+          roles.push_back(ip >= 0 ? pi[ip] : -1);
+          vecs.push_back(Acur[q][j].diag);
+          vecs.push_back(Ccur[q][im].diag);
+          vecs.push_back(ip >= 0 ? Ccur[q][j].diag : nullptr);
+          vecs.push_back(ip >= 0 ? Acur[q][ip].diag : nullptr);
+          if (Acur[q][im].kind) {  // A_j <- -diag(a_j) Dinv_{j-1} diag(a_{j-1})
+            int id = new_instance(s);
+            An[q][j] = Coupling{2, id, nullptr};
+            roles2.push_back(id);
+            roles2.push_back(pi[im]);
+            vecs2.push_back(Acur[q][j].diag);
+            vecs2.push_back(Acur[q][im].diag);
+          }
+          if (ip >= 0 && Ccur[q][ip].kind) {  // C_j <- -diag(c_j) Dinv_{j+1} diag(c_{j+1})
+            int id = new_instance(s);
+            Cn[q][j] = Coupling{2, id, nullptr};
+            roles2.push_back(id);
+            roles2.push_back(pi[ip]);
+            vecs2.push_back(Ccur[q][j].diag);
+            vecs2.push_back(Ccur[q][ip].diag);
+          }
+        }
+      }
+      run_program(get_program("copy_schur"), (int)roles.size() / 3, 3, roles, 4, vecs, s);
+      run_program(get_program("copy_direct"), (int)roles2.size() / 2, 2, roles2, 2, vecs2, s);
+    } else {
+      std::vector<int32_t> rXY, rS, rN;
+      std::vector<int> tmp;
+      for (int q = 0; q < np; ++q) {
+        const auto& pi = probs[q].plane_inst;
+        for (size_t m = 0; m < L.K.size(); ++m) {
+          const int pos = 2 * (int)m + 1;
+          const int j = P[pos], im = P[pos - 1];
+          const int ip = pos + 1 < (int)P.size() ? P[pos + 1] : -1;
+          const int X = new_instance(s);
+          tmp.push_back(X);
+          rXY.insert(rXY.end(), {X, Acur[q][j].inst, pi[im]});
+          int Y = -1;
+          if (ip >= 0) {
+            Y = new_instance(s);
+            tmp.push_back(Y);
+            rXY.insert(rXY.end(), {Y, Ccur[q][j].inst, pi[ip]});
+          }
+          rS.insert(rS.end(), {pi[j], X, Ccur[q][im].inst, Y, ip >= 0 ? Acur[q][ip].inst : -1});
+          if (Acur[q][im].kind) {
+            int id = new_instance(s);
+            An[q][j] = Coupling{2, id, nullptr};
+            rN.insert(rN.end(), {id, X, Acur[q][im].inst});
+          }
+          if (ip >= 0 && Ccur[q][ip].kind) {
+            int id = new_instance(s);
+            Cn[q][j] = Coupling{2, id, nullptr};
+            rN.insert(rN.end(), {id, Y, Ccur[q][ip].inst});
+          }
+        }
+      }
+      run_program(get_program("mul_new"), (int)rXY.size() / 3, 3, rXY, 0, {}, s);
+      run_program(get_program("schur2"), (int)rS.size() / 5, 5, rS, 0, {}, s);
+      run_program(get_program("mul_neg"), (int)rN.size() / 3, 3, rN, 0, {}, s);
+      HIPCHK(hipStreamSynchronize(s));
+      for (int t : tmp) release_instance(t);
+    }
+    for (int q = 0; q < np; ++q)
+      for (int j : L.K) {
+        Acur[q][j] = An[q][j];
+        Ccur[q][j] = Cn[q][j];
+      }
+    P = L.K;
+    ++lev;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (int t : tpool) release_instance(t);
+}
+
+// ------------------------------------------------------------ apply
+static MvTerm term_of(const Coupling& c, const double* x, double alpha, int trans) {
+  MvTerm t{};
+  t.alpha = alpha;
+  t.trans = trans;
+  t.x = x;
+  t.inst = -1;
+  t.dvec = nullptr;
+  if (c.kind == 1) t.dvec = c.diag;
+  if (c.kind == 2) t.inst = c.inst;
+  return t;
+}
+
+void Handle::build_apply_jobs() {
+  auto clear = [&](std::vector<PhaseJobs>& ph) {
+    for (auto& p : ph)
+      if (p.d) dfree(p.d);
+    ph.clear();
+  };
+  clear(ph_apply);
+  clear(ph_applyT);
+  for (Prob& P : probs) {
+    clear(P.ph_apply);
+    clear(P.ph_applyT);
+  }
+  const int np = (int)probs.size();
+  if (!g) {
+    g = dnew<double>((size_t)N * np);
+    w = dnew<double>((size_t)N * np);
+    z = dnew<double>((size_t)N * np);
+  }
+  auto V = [&](double* base, int q, int plane) { return base + (int64_t)q * N + (int64_t)plane * B; };
+  const MvTerm none{-1, 0, 0.0, nullptr, nullptr};
+  max_jobs = 0;
+  // phases of problem q (q < 0: all problems concatenated per phase)
+  auto build = [&](int qsel, int tr, std::vector<PhaseJobs>& out) {
+    std::vector<std::vector<MvJob>> phases;
+    const Prob& P0 = probs[0];
+    const int nlev = (int)P0.levels.size();
+    auto add = [&](size_t ph, const MvJob& J) {
+      if (phases.size() <= ph) phases.resize(ph + 1);
+      phases[ph].push_back(J);
+    };
+    for (int q = 0; q < np; ++q) {
+      if (qsel >= 0 && q != qsel) continue;
+      const Prob& pr = probs[q];
+      size_t ph = 0;
+      for (int r = 0; r < nlev; ++r, ph += 2) {  // forward elimination
+        const Level& L = pr.levels[r];
+        const auto& Pl = L.P;
+        for (int i : L.E) {
+          MvJob J{};
+          J.y = V(w, q, i);
+          J.base = nullptr;
+          J.t[0] = MvTerm{L.dinv.at(i), tr, 1.0, V(g, q, i), nullptr};
+          J.t[1] = none;
+          add(ph, J);
+        }
+        for (size_t m = 0; m < L.K.size(); ++m) {
+          const int pos = 2 * (int)m + 1;
+          const int j = Pl[pos], im = Pl[pos - 1];
+          const int ip = pos + 1 < (int)Pl.size() ? Pl[pos + 1] : -1;
+          MvJob J{};
+          J.y = V(g, q, j);
+          J.base = V(g, q, j);
+          if (!tr) {
+            J.t[0] = term_of(L.A.at(j), V(w, q, im), -1.0, 0);
+            J.t[1] = ip >= 0 ? term_of(L.C.at(j), V(w, q, ip), -1.0, 0) : none;
+          } else {
+            J.t[0] = term_of(L.C.at(im), V(w, q, im), -1.0, 1);
+            J.t[1] = ip >= 0 ? term_of(L.A.at(ip), V(w, q, ip), -1.0, 1) : none;
+          }
+          add(ph + 1, J);
+        }
+      }
+      {  // top plane
+        MvJob J{};
+        J.y = V(z, q, pr.top_plane);
+        J.base = nullptr;
+        J.t[0] = MvTerm{pr.top_inst, tr, 1.0, V(g, q, pr.top_plane), nullptr};
+        J.t[1] = none;
+        add(ph, J);
+        ph += 1;
+      }
+      for (int r = nlev - 1; r >= 0; --r, ph += 2) {  // back substitution
+        const Level& L = pr.levels[r];
+        const auto& Pl = L.P;
+        for (size_t m = 0; m < L.E.size(); ++m) {
+          const int pos = 2 * (int)m;
+          const int i = Pl[pos];
+          const int im = pos > 0 ? Pl[pos - 1] : -1;
+          const int ip = pos + 1 < (int)Pl.size() ? Pl[pos + 1] : -1;
+          MvJob J{};
+          J.y = V(w, q, i);
+          J.base = V(g, q, i);
+          if (!tr) {
+            J.t[0] = im >= 0 ? term_of(L.A.at(i), V(z, q, im), -1.0, 0) : none;
+            J.t[1] = ip >= 0 ? term_of(L.C.at(i), V(z, q, ip), -1.0, 0) : none;
+          } else {
+            J.t[0] = im >= 0 ? term_of(L.C.at(im), V(z, q, im), -1.0, 1) : none;
+            J.t[1] = ip >= 0 ? term_of(L.A.at(ip), V(z, q, ip), -1.0, 1) : none;
+          }
+          add(ph, J);
+          MvJob K{};
+          K.y = V(z, q, i);
+          K.base = nullptr;
+          K.t[0] = MvTerm{L.dinv.at(i), tr, 1.0, V(w, q, i), nullptr};
+          K.t[1] = none;
+          add(ph + 1, K);
+        }
+      }
+    }
+    for (auto& jobs : phases) {
+      if (jobs.empty()) continue;
+      PhaseJobs pj;
+      pj.d = upload(jobs);
+      pj.n = (int)jobs.size();
+      max_jobs = std::max(max_jobs, pj.n);
+      out.push_back(pj);
+    }
+  };
+  build(-1, 0, ph_apply);
+  build(-1, 1, ph_applyT);
+  if (np > 1)
+    for (int q = 0; q < np; ++q) {
+      build(q, 0, probs[q].ph_apply);
+      build(q, 1, probs[q].ph_applyT);
+    }
+  if (coef) dfree(coef);
+  coef = dnew<double>((size_t)std::max(max_jobs, 1) * 2 * sstride);
+}
+
+void Handle::apply(const std::vector<const double*>& r, const std::vector<double*>& out, bool transpose, int prob,
+                   hipStream_t s) {
+  sync_tables();
+  const int np = (int)probs.size();
+  for (int q = 0; q < np; ++q)
+    if (prob < 0 || q == prob) launch_to_horder(r[q], g + (int64_t)q * N, d_perm, B, N, s);
+  const std::vector<PhaseJobs>* ph;
+  if (prob < 0 || np == 1)
+    ph = transpose ? &ph_applyT : &ph_apply;
+  else
+    ph = transpose ? &probs[prob].ph_applyT : &probs[prob].ph_apply;
+  for (const PhaseJobs& pj : *ph) {
+    if (fp32) {
+      MvArgs<float> a{};
+      a.leaves = d_leaves;
+      a.lr_leaves = d_lr_leaves;
+      a.soff = d_soff;
+      a.nlr = G.nlr;
+      a.sstride = sstride;
+      a.jobs = pj.d;
+      a.njobs = pj.n;
+      a.inst_base = (float* const*)d_inst_base;
+      a.inst_rank = d_inst_rank;
+      a.coef = coef;
+      a.seg_lo = d_seg_lo;
+      a.rows_ptr = d_rows_ptr;
+      a.rows_idx = d_rows_idx;
+      a.cols_ptr = d_cols_ptr;
+      a.cols_idx = d_cols_idx;
+      a.nseg = (int)G.leaf_clusters.size();
+      launch_mv<float>(a, s);
+    } else {
+      MvArgs<double> a{};
+      a.leaves = d_leaves;
+      a.lr_leaves = d_lr_leaves;
+      a.soff = d_soff;
+      a.nlr = G.nlr;
+      a.sstride = sstride;
+      a.jobs = pj.d;
+      a.njobs = pj.n;
+      a.inst_base = (double* const*)d_inst_base;
+      a.inst_rank = d_inst_rank;
+      a.coef = coef;
+      a.seg_lo = d_seg_lo;
+      a.rows_ptr = d_rows_ptr;
+      a.rows_idx = d_rows_idx;
+      a.cols_ptr = d_cols_ptr;
+      a.cols_idx = d_cols_idx;
+      a.nseg = (int)G.leaf_clusters.size();
+      launch_mv<double>(a, s);
+    }
+  }
+  for (int q = 0; q < np; ++q)
+    if (prob < 0 || q == prob) launch_from_horder(z + (int64_t)q * N, out[q], d_perm, B, N, s);
+  HIPCHK(hipGetLastError());
+}
+
+void Handle::matvec(int prob, const double* x, double* y, bool transpose, hipStream_t s) {
+  launch_stencil_mv(probs[prob].S, nx, ny, nz, transpose ? 1 : 0, x, y, s);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ statistics
+double Handle::instance_bytes(const std::vector<int32_t>& rk) const {
+  const double esz = fp32 ? 4.0 : 8.0;
+  double b = 0.0;
+  for (size_t l = 0; l < G.lf.size(); ++l) {
+    const Leaf& L = G.lf[l];
+    if (L.fmt == LF_DENSE)
+      b += (double)L.m * L.n * esz;
+    else
+      b += (double)(L.m + L.n) * rk[l] * esz;
+  }
+  return b;
+}
+
+void Handle::compute_stats() {
+  acr_stats_t s{};
+  s.levels = (int)probs[0].levels.size() + 1;
+  s.nplanes = nz;
+  s.plane_points = B;
+  s.clusters = (int)G.cl.size();
+  s.dense_leaves = G.ndense;
+  s.lr_leaves = G.nlr;
+  s.precision = opt.precision;
+  double total = 0.0, apply_bytes = 0.0;
+  double rank_cnt[ACR_MAX_LEVELS] = {0};
+  int nf = 0;
+  std::vector<int32_t> rk(G.lf.size());
+  auto level_of = [&](int r, int id, double weight) {
+    HIPCHK(hipMemcpy(rk.data(), inst[id].rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const double b = instance_bytes(rk);
+    total += b;
+    apply_bytes += weight * b;
+    ++nf;
+    int mx = 0;
+    double sum = 0;
+    int cnt = 0;
+    for (size_t l = 0; l < G.lf.size(); ++l)
+      if (G.lf[l].fmt == LF_LR) {
+        mx = std::max(mx, (int)rk[l]);
+        sum += rk[l];
+        ++cnt;
+      }
+    if (r < ACR_MAX_LEVELS) {
+      s.max_rank[r] = std::max(s.max_rank[r], mx);
+      s.mean_rank[r] += sum;
+      rank_cnt[r] += cnt;
+    }
+  };
+  for (const Prob& P : probs) {
+    for (size_t r = 0; r < P.levels.size(); ++r) {
+      const Level& L = P.levels[r];
+      for (auto& kv : L.dinv) level_of((int)r, kv.second, 2.0);
+      for (int p : L.P)
+        for (const Coupling* c : {&L.A.at(p), &L.C.at(p)}) {
+          if (c->kind == 2) level_of((int)r, c->inst, 1.0);
+          if (c->kind == 1) apply_bytes += (double)B * 8.0;
+        }
+    }
+    level_of((int)P.levels.size(), P.top_inst, 1.0);
+    // vectors: every job reads its inputs and writes its output plane
+    apply_bytes += 2.0 * (double)N * 8.0 * 2.0 * (double)P.levels.size() + 2.0 * (double)N * 8.0;
+  }
+  for (int r = 0; r < ACR_MAX_LEVELS; ++r)
+    if (rank_cnt[r] > 0) s.mean_rank[r] /= rank_cnt[r];
+  for (int r = 0; r < ACR_MAX_LEVELS; ++r) s.max_rank_all = std::max(s.max_rank_all, s.max_rank[r]);
+  s.factors = nf;
+  s.bytes_factors = total;
+  s.bytes_allocated = (double)bytes_alloc;
+  s.bytes_per_apply = apply_bytes;
+  st = s;
+}
+
+}  // namespace acr

@@ -24,7 +24,8 @@ struct KWork {
   Handle& h;
   hipStream_t s;
   int64_t N;
-  KWork(Handle& hh, hipStream_t ss) : h(hh), s(ss), N(hh.N) {}
+  int prob;
+  KWork(Handle& hh, hipStream_t ss, int p) : h(hh), s(ss), N(hh.N), prob(p) {}
 
   void ensure(size_t nvec) {
     if (h.kv_len >= nvec) return;
@@ -51,15 +52,21 @@ struct KWork {
     HIPCHK(hipStreamSynchronize(s));
     for (int d = 0; d < nd; ++d) out[d] = h.hres[d];
   }
-  void A(const double* x, double* y, bool tr) { h.matvec(x, y, tr, s); }
-  void M(const double* x, double* y, bool tr) { h.apply(x, y, tr, s); }
+  void A(const double* x, double* y, bool tr) { h.matvec(prob, x, y, tr, s); }
+  void M(const double* x, double* y, bool tr) {
+    std::vector<const double*> in(h.probs.size(), nullptr);
+    std::vector<double*> out(h.probs.size(), nullptr);
+    in[prob] = x;
+    out[prob] = y;
+    h.apply(in, out, tr, prob, s);
+  }
 };
 
 }  // namespace
 
-acr_status krylov_cg(Handle& h, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
+acr_status krylov_cg(Handle& h, int prob, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
                      acr_solve_info* info, hipStream_t s) {
-  KWork k(h, s);
+  KWork k(h, s, prob);
   k.ensure(5);
   double *r = k.vec(0), *zz = k.vec(1), *p = k.vec(2), *Ap = k.vec(3), *zold = k.vec(4);
   const int64_t N = h.N;
@@ -149,9 +156,9 @@ acr_status krylov_cg(Handle& h, bool flexible, bool tr, double rtol, int maxit, 
   return stt;
 }
 
-acr_status krylov_gmres(Handle& h, int m, bool tr, double rtol, int maxit, const double* b, double* x,
+acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int maxit, const double* b, double* x,
                         acr_solve_info* info, hipStream_t s) {
-  KWork k(h, s);
+  KWork k(h, s, prob);
   // layout: V[0..m] (m+1 vectors), Z[0..m-1] (m vectors), r, w
   k.ensure(2 * (size_t)m + 3);
   const int64_t N = h.N;

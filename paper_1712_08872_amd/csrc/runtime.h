@@ -86,13 +86,29 @@ struct PhaseJobs {           // device job array of one apply phase
   int n = 0;
 };
 
+// One problem of a handle.  All problems of a handle share the plane shape
+// (nx, ny) and the number of planes nz, hence the geometry, the programs and
+// the cyclic-reduction structure: their levels run in lockstep and every
+// batched launch covers all of them.
+struct Prob {
+  int kind = 0;
+  double beta_amp = 0, beta_phase = 0, omega = 0;
+  double* S = nullptr;       // 7 * N assembled stencil
+  double* kappa = nullptr;   // node-grid copy (Poisson / convection-diffusion)
+  double *zA = nullptr, *zC = nullptr;  // H-ordered level-0 z-couplings
+  std::vector<Level> levels;
+  int top_plane = -1, top_inst = -1;
+  std::vector<int> plane_inst;          // current D / Dinv instance of each plane
+  std::vector<PhaseJobs> ph_apply, ph_applyT;  // this problem alone (Krylov)
+};
+
 struct Handle {
-  // problem
-  int nx = 0, ny = 0, nz = 0, kind = 0, B = 0;
-  int64_t N = 0;
+  // shape shared by the problems
+  int nx = 0, ny = 0, nz = 0, B = 0;
+  int64_t N = 0;               // unknowns of one problem
   acr_options opt{};
   bool fp32 = false;
-  double beta_amp = 0, beta_phase = 0, omega = 0;
+  std::vector<Prob> probs;
   // allocator
   std::vector<std::pair<void*, size_t>> owned;
   size_t bytes_alloc = 0;
@@ -105,9 +121,6 @@ struct Handle {
     HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
     return p;
   }
-  // assembled operator and inputs kept by the handle
-  double* S = nullptr;       // 7 * N
-  double* kappa = nullptr;   // node grid copy (Poisson/convdiff)
   // geometry and device tables
   Geometry G;
   DLeaf* d_leaves = nullptr;
@@ -128,7 +141,6 @@ struct Handle {
   void release_instance(int id);
   void sync_tables();
   // programs
-  Program inv_prog;
   std::map<std::string, Program> prog;
   Program& get_program(const std::string& key);
   void upload_program(Program& p);
@@ -148,15 +160,10 @@ struct Handle {
   int roles_cap = 0;
   const double** d_vecs = nullptr;
   int vecs_cap = 0;
-  // cyclic reduction structure
-  std::vector<Level> levels;
-  int top_plane = -1, top_inst = -1;
-  double *zA = nullptr, *zC = nullptr;
-  std::vector<int> plane_inst;  // current D / Dinv instance of each plane
-  // apply workspace
+  // apply workspace (all problems, plane vectors concatenated by problem)
   double *g = nullptr, *w = nullptr, *z = nullptr, *coef = nullptr;
   int max_jobs = 0;
-  std::vector<PhaseJobs> ph_apply, ph_applyT;
+  std::vector<PhaseJobs> ph_apply, ph_applyT;  // all problems at once
   // krylov workspace
   double *kv = nullptr, *part = nullptr, *dres = nullptr;
   const double **dots_a = nullptr, **dots_b = nullptr;
@@ -164,23 +171,30 @@ struct Handle {
   size_t kv_len = 0;
   // statistics
   acr_stats_t st{};
-  int retries = 0;
 
   ~Handle();
-  void setup(const acr_problem* p, hipStream_t s);
+  void setup(const acr_problem* ps, int count, hipStream_t s);
   void build_factors(hipStream_t s, const std::vector<int>& caps);
   void free_factors();
   void run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
                    const std::vector<const double*>& vecs, hipStream_t s);
   void build_apply_jobs();
-  void apply(const double* r, double* z, bool transpose, hipStream_t s);
-  void matvec(const double* x, double* y, bool transpose, hipStream_t s);
+  // z_p = M_p^{-1} r_p (or M_p^{-T}) for every problem (prob < 0) or one
+  void apply(const std::vector<const double*>& r, const std::vector<double*>& z, bool transpose, int prob,
+             hipStream_t s);
+  void matvec(int prob, const double* x, double* y, bool transpose, hipStream_t s);
   void compute_stats();
-  double instance_bytes(int id, const std::vector<int32_t>& ranks) const;
+  double instance_bytes(const std::vector<int32_t>& ranks) const;
 };
 
 }  // namespace acr
 
+// A handle holds one or more groups of problems; the problems of a group
+// share a plane shape.  Vectors passed through the ABI concatenate the
+// problems in the order they were given.
 struct acr_handle {
-  acr::Handle h;
+  std::vector<std::unique_ptr<acr::Handle>> groups;
+  std::vector<std::pair<int, int>> where;  // problem -> (group, index in group)
+  std::vector<int64_t> off, grid_off;      // vector / node-grid offsets per problem
+  int64_t total = 0, grid_total = 0;
 };
