@@ -128,6 +128,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
     accum_launches = 0;
     ev_used = 0;
+    ev_tag.clear();
     for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
     HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   }
@@ -148,6 +149,19 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
       ms += t;
     }
     st.accum_seconds = ms * 1e-3;
+    if (const char* path = getenv("ACR_TIMING_LOG"); path && path[0]) {
+      // one line per accumulation launch: program, CR level, step, batch, targets, widest target, ms
+      if (FILE* f = fopen(path, "w")) {
+        fprintf(f, "prog,level,step,nbatch,nt,max_m,ms\n");
+        for (size_t i = 0; i + 1 < ev_used && i / 2 < ev_tag.size(); i += 2) {
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, ev_pool[i], ev_pool[i + 1]));
+          const LaunchTag& g = ev_tag[i / 2];
+          fprintf(f, "%s,%d,%d,%d,%d,%d,%.4f\n", g.prog, g.level, g.step, g.nbatch, g.nt, g.max_m, t);
+        }
+        fclose(f);
+      }
+    }
     HIPCHK(hipMemcpy(&st.accum_flops, d_flops, sizeof(double), hipMemcpyDeviceToHost));
     st.setup_flops = st.accum_flops;
   }
@@ -234,7 +248,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     int mm = std::max(G.max_dense_rows, G.max_lr_dim), nn = std::max(G.max_dense_cols, G.max_lr_dim);
     // narrow rounds (more resident blocks per CU) when every capacity fits
     kc = (*std::max_element(caps.begin(), caps.end()) <= 30) ? 38 : 64;
-    int64_t stride = (int64_t)(mm + nn) * kc;
+    int64_t stride = (int64_t)(mm + nn) * kc + DACC_ELEMS;  // + dense accumulator of small low-rank targets
     stride = ((stride + 63) / 64) * 64;
     if (stride > scratch_stride || !scratch) {
       if (scratch) dfree(scratch);
@@ -285,6 +299,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
   for (int k = 0; k < nz; ++k) P[k] = k;
   int lev = 0;
   while (true) {
+    cur_level = lev;
     if (P.size() == 1) {
       inverse_batch(P);
       for (Prob& pr : probs) {

@@ -62,6 +62,7 @@ __device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
 }
 
 constexpr int ROUND = 32;  // columns appended between recompressions
+constexpr int DACC_MAX = DACC_ELEMS;  // largest m*n of a low-rank target accumulated densely
 constexpr int LDM = KC + 1;  // padded leading dimension of the K x K matrices (no LDS bank conflicts)
 
 struct Lds {
@@ -708,6 +709,63 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
   }
 }
 
+// Dense accumulation C += sum of the target's pieces (C column-major,
+// leading dimension tc.m).  Low-rank pieces are expanded `take` columns at a
+// time into the staging columns [0, take) of Us / Vs and added as outer
+// products.
+template <typename T>
+__device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
+                             Lds& L) {
+  const int tid = threadIdx.x;
+  for (int p = tg.p0; p < tg.p1; ++p) {
+    const Piece P = A.pieces[p];
+    if (P.kind == PK_DD) {
+      const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
+      if (xi < 0 || yi < 0) continue;
+      const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
+      const T* xp = leaf_base(A, xi, P.xleaf);
+      const T* yp = leaf_base(A, yi, P.yleaf);
+      const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
+      for (int cc0 = P.wc0; cc0 < P.wc1; cc0 += KC) {
+        const int nc = imin(KC, P.wc1 - cc0);
+        for (int qc = M0; qc < M1; qc += KC) {
+          const int nqc = imin(KC, M1 - qc);
+          for (int idx = tid; idx < nqc * nc; idx += TPB) {
+            const int q = idx % nqc, jj = idx / nqc;
+            L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * y.m];
+          }
+          __syncthreads();
+          nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, nc,
+                 C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
+          FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
+        }
+      }
+    } else if (P.kind == PK_COPY && A.leaves[P.xleaf].fmt == 0) {
+      const int si = inst_of(A, b, P.xrole);
+      if (si < 0) continue;
+      const T* src = leaf_base(A, si, P.xleaf);
+      const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
+      const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
+      for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+        int i = idx % tc.m, c = idx / tc.m;
+        double v = P.alpha * (double)src[idx];
+        if (rho) v *= rho[tc.r0 + i];
+        if (gam) v *= gam[tc.c0 + c];
+        C[idx] = (T)((double)C[idx] + v);
+      }
+      __syncthreads();
+    } else {
+      const int w = piece_width(A, b, P);
+      for (int j0 = 0; j0 < w; j0 += KC) {
+        int take = imin(KC, w - j0);
+        piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
+        dense_add_outer(C, tc, Us, Vs, take, L);
+        FLOP(L, 2.0 * tc.m * tc.n * take);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------ main kernel
 template <typename T>
 __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
@@ -733,53 +791,7 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
       if (!tg.beta)
         for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
       __syncthreads();
-      for (int p = tg.p0; p < tg.p1; ++p) {
-        const Piece P = A.pieces[p];
-        if (P.kind == PK_DD) {
-          const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
-          if (xi < 0 || yi < 0) continue;
-          const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
-          const T* xp = leaf_base(A, xi, P.xleaf);
-          const T* yp = leaf_base(A, yi, P.yleaf);
-          const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
-          for (int cc0 = P.wc0; cc0 < P.wc1; cc0 += KC) {
-            const int nc = imin(KC, P.wc1 - cc0);
-            for (int qc = M0; qc < M1; qc += KC) {
-              const int nqc = imin(KC, M1 - qc);
-              for (int idx = tid; idx < nqc * nc; idx += TPB) {
-                const int q = idx % nqc, jj = idx / nqc;
-                L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * y.m];
-              }
-              __syncthreads();
-              nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, nc,
-                     C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
-              FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
-            }
-          }
-        } else if (P.kind == PK_COPY) {
-          const int si = inst_of(A, b, P.xrole);
-          if (si < 0) continue;
-          const T* src = leaf_base(A, si, P.xleaf);
-          const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
-          const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
-          for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
-            int i = idx % tc.m, c = idx / tc.m;
-            double v = P.alpha * (double)src[idx];
-            if (rho) v *= rho[tc.r0 + i];
-            if (gam) v *= gam[tc.c0 + c];
-            C[idx] = (T)((double)C[idx] + v);
-          }
-          __syncthreads();
-        } else {
-          const int w = piece_width(A, b, P);
-          for (int j0 = 0; j0 < w; j0 += KC) {
-            int take = imin(KC, w - j0);
-            piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
-            dense_add_outer(C, tc, Us, Vs, take, L);
-            FLOP(L, 2.0 * tc.m * tc.n * take);
-          }
-        }
-      }
+      dense_pieces(A, b, tg, tc, C, Us, Vs, L);
       PROF_ADD(PS_DENSE, clock64() - tdense0);
       continue;
     }
@@ -813,27 +825,34 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
     }
     int K = 0;
     int kbase = 0;  // rank after the last recompression
-    if (tg.beta) {
-      const int k0 = *rk;
-      for (int idx = tid; idx < tc.m * k0; idx += TPB) {
-        int i = idx % tc.m, j = idx / tc.m;
-        Us[(int64_t)i * KC + j] = Uc[idx];
+    const int k0 = tg.beta ? *rk : 0;
+    // Small targets that receive more columns than their smaller dimension
+    // are accumulated exactly as a dense m x n block and compressed once:
+    // fewer recompressions, and the sum is truncated only at the end.
+    if (tid == 0) L.ival[5] = 0;
+    __syncthreads();
+    if (tc.m * tc.n <= DACC_MAX)
+      for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&L.ival[5], piece_width(A, b, A.pieces[p]));
+    __syncthreads();
+    const bool dacc = tc.m * tc.n <= DACC_MAX && L.ival[5] > imin(tc.m, tc.n);
+    if (dacc) {
+      T* D = Us + (int64_t)(tc.m + tc.n) * KC;  // m x n, column-major
+      for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+        const int i = idx % tc.m, c = idx / tc.m;
+        double v = 0.0;
+        for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
+        D[idx] = (T)v;
       }
-      for (int idx = tid; idx < tc.n * k0; idx += TPB) {
-        int c = idx % tc.n, j = idx / tc.n;
-        Vs[(int64_t)c * KC + j] = Vc[idx];
-      }
-      K = k0;
-      kbase = k0;
+      FLOP(L, 2.0 * tc.m * tc.n * k0);
       __syncthreads();
-    }
-    for (int p = tg.p0; p < tg.p1; ++p) {
-      const Piece P = A.pieces[p];
-      const int w = piece_width(A, b, P);
-      int j0 = 0;
-      while (j0 < w) {
-        // recompress once ROUND columns have been appended beyond the current
-        // rank (the cost of a recompression grows with the cube of its width)
+      const long long tp0 = clock64();
+      dense_pieces(A, b, tg, tc, D, Us, Vs, L);
+      PROF_ADD(PS_PIECES_LR, clock64() - tp0);
+      // D = U V^T along the smaller dimension: rows (U = identity columns,
+      // V = rows of D) when m <= n, else columns (U = columns of D, V = identity)
+      const bool by_rows = tc.m <= tc.n;
+      const int sdim = by_rows ? tc.m : tc.n;
+      for (int j0 = 0; j0 < sdim;) {
         const int klim = imin(KC, kbase + ROUND);
         if (K >= klim) {
           K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
@@ -843,12 +862,56 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           }
           kbase = K;
         }
-        int take = imin(w - j0, imin(KC, kbase + ROUND) - K);
-        const long long tp0 = clock64();
-        piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
-        PROF_ADD(PS_PIECES_LR, clock64() - tp0);
+        const int take = imin(sdim - j0, imin(KC, kbase + ROUND) - K);
+        for (int idx = tid; idx < tc.m * take; idx += TPB) {
+          const int i = idx / take, jj = idx - i * take;
+          Us[(int64_t)i * KC + K + jj] = by_rows ? (T)(i == j0 + jj ? 1.0 : 0.0) : D[i + (int64_t)(j0 + jj) * tc.m];
+        }
+        for (int idx = tid; idx < tc.n * take; idx += TPB) {
+          const int c = idx / take, jj = idx - c * take;
+          Vs[(int64_t)c * KC + K + jj] = by_rows ? D[(j0 + jj) + (int64_t)c * tc.m] : (T)(c == j0 + jj ? 1.0 : 0.0);
+        }
+        __syncthreads();
         K += take;
         j0 += take;
+      }
+    } else {
+      if (tg.beta) {
+        for (int idx = tid; idx < tc.m * k0; idx += TPB) {
+          int i = idx % tc.m, j = idx / tc.m;
+          Us[(int64_t)i * KC + j] = Uc[idx];
+        }
+        for (int idx = tid; idx < tc.n * k0; idx += TPB) {
+          int c = idx % tc.n, j = idx / tc.n;
+          Vs[(int64_t)c * KC + j] = Vc[idx];
+        }
+        K = k0;
+        kbase = k0;
+        __syncthreads();
+      }
+      for (int p = tg.p0; p < tg.p1; ++p) {
+        const Piece P = A.pieces[p];
+        const int w = piece_width(A, b, P);
+        int j0 = 0;
+        while (j0 < w) {
+          // recompress once ROUND columns have been appended beyond the current
+          // rank (the cost of a recompression grows with the cube of its width)
+          const int klim = imin(KC, kbase + ROUND);
+          if (K >= klim) {
+            K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
+            if (K > KC - 8) {
+              if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
+              K = KC - 8;
+            }
+            kbase = K;
+          }
+          int take = imin(w - j0, imin(KC, kbase + ROUND) - K);
+          const long long tp0 = clock64();
+          piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
+          PROF_ADD(PS_PIECES_LR, clock64() - tp0);
+          K += take;
+          j0 += take;
+        }
       }
     }
     if (tg.p1 > tg.p0 || !tg.beta) {

@@ -1,6 +1,7 @@
 // Host-side expansion of H-arithmetic into batched device steps.
 #pragma once
 #include <map>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct Program {
   Target* d_targets = nullptr;
   int32_t* d_lists = nullptr;
   int max_m = 0, max_n = 0;
+  std::string name;
 };
 
 // Collects the pieces of one device step: any number of formatted products

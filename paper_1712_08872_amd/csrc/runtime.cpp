@@ -155,6 +155,7 @@ Program& Handle::get_program(const std::string& key) {
     }
     sb.finish_step();
   }
+  P.name = key;
   upload_program(P);
   auto res = prog.emplace(key, std::move(P));
   return res.first->second;
@@ -181,7 +182,8 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
     }
     HIPCHK(hipMemcpy((void*)d_vecs, vecs.data(), vecs.size() * sizeof(double*), hipMemcpyHostToDevice));
   }
-  for (const Step& st : P.steps) {
+  for (size_t si = 0; si < P.steps.size(); ++si) {
+    const Step& st = P.steps[si];
     if (st.type == 1) {
       const Leaf& L = G.lf[st.leaf];
       if (fp32)
@@ -220,6 +222,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
           ev_pool.push_back(e);
         }
         HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+        ev_tag.push_back({P.name.c_str(), cur_level, (int)si, nbatch, st.nt, st.max_m});
       }
       if (kc == 38)
         kc38::launch_accum<float>(a, grid, s);
@@ -258,6 +261,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
           ev_pool.push_back(e);
         }
         HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+        ev_tag.push_back({P.name.c_str(), cur_level, (int)si, nbatch, st.nt, st.max_m});
       }
       if (kc == 38)
         kc38::launch_accum<double>(a, grid, s);

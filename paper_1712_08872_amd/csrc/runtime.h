@@ -155,6 +155,12 @@ struct Handle {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  struct LaunchTag {
+    const char* prog;
+    int level, step, nbatch, nt, max_m;
+  };
+  std::vector<LaunchTag> ev_tag;  // one per timed launch (ACR_KERNEL_TIMING=1)
+  int cur_level = -1;
   int accum_launches = 0;
   int32_t* d_roles = nullptr;
   int roles_cap = 0;
