@@ -90,7 +90,12 @@ typedef struct {
     double eta;                /* admissibility parameter, > 0 */
     int32_t leaf_size;         /* n_min: cluster leaves have <= leaf_size points (8..64) */
     int32_t precision;         /* acr_precision */
-    int32_t max_rank;          /* initial rank capacity of low-rank blocks; 0 = automatic */
+    int32_t max_rank;          /* rank cap of the low-rank blocks (<= 56).  0 = automatic: the
+                                  capacity starts at 6 + 6 log10(1/eps) and the setup is redone
+                                  with larger capacities when a rank overflows.  > 0: a fixed
+                                  cap; ranks are clamped to it and acr_stats reports
+                                  rank_overflow = 1 (the factors are then less accurate than
+                                  eps, a Krylov solve still converges) */
     int32_t dense_work;        /* admissible blocks with min dimension <= dense_work are kept
                                   dense (exact) during setup; 0 = paper's format everywhere */
     acr_alloc_fn alloc;        /* optional device allocator (NULL -> hipMalloc) */
@@ -131,6 +136,9 @@ typedef struct {
     int32_t accum_launches;
     double accum_seconds;
     double accum_flops;
+    double bytes_peak;                     /* largest device footprint reached during setup (a
+                                              batched handle with several shape groups: the sum
+                                              of the groups' peaks, an upper bound) */
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

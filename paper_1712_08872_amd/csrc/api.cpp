@@ -330,6 +330,7 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
   // one group: its statistics; several groups: sums and maxima
   *st = h->groups[0]->st;
   st->bytes_allocated = (double)h->groups[0]->bytes_alloc;
+  st->bytes_peak = (double)h->groups[0]->bytes_peak;
   for (size_t g = 1; g < h->groups.size(); ++g) {
     const acr_stats_t& o = h->groups[g]->st;
     st->factors += o.factors;
@@ -339,6 +340,7 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
     st->max_rank_all = std::max(st->max_rank_all, o.max_rank_all);
     st->bytes_factors += o.bytes_factors;
     st->bytes_allocated += (double)h->groups[g]->bytes_alloc;
+    st->bytes_peak += (double)h->groups[g]->bytes_peak;
     st->bytes_per_apply += o.bytes_per_apply;
     st->setup_seconds += o.setup_seconds;
     st->setup_flops += o.setup_flops;

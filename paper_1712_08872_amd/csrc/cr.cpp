@@ -116,21 +116,38 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     if (hflags[FL_SINGULAR]) throw AcrError(ACR_E_SINGULAR, "exactly singular dense leaf in an H-inverse");
     if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite value during setup");
+    if (hflags[FL_LAYOUT]) throw AcrError(ACR_E_DEVICE, "internal: packed instance used as a target");
     int cmax = *std::max_element(caps.begin(), caps.end());
-    if (!hflags[FL_RANK_OVERFLOW] || cmax >= KC_MAX - 8 || attempt >= 3) {
+    // a caller-given max_rank is a fixed cap: ranks are clamped to it and
+    // the overflow is reported, not retried
+    if (!hflags[FL_RANK_OVERFLOW] || opt.max_rank > 0 || cmax >= KC_MAX - 8 || attempt >= 3) {
       st.max_rank_all = hflags[FL_MAXRANK];
       st.retries = attempt;
       if (hflags[FL_RANK_OVERFLOW]) st.rank_overflow = 1;
       break;
     }
-    // rank capacity exhausted: redo with larger capacities
+    // rank capacity exhausted: redo with larger capacities (the pooled
+    // capacity buffers have the old layout)
     free_factors();
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* b : cap_pool) dfree(b);
+    cap_pool.clear();
     if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
     accum_launches = 0;
     ev_used = 0;
     ev_tag.clear();
     for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
     HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  }
+  // working memory of the setup: recycled capacity buffers and the
+  // accumulation scratch
+  HIPCHK(hipStreamSynchronize(s));
+  for (void* b : cap_pool) dfree(b);
+  cap_pool.clear();
+  if (scratch) {
+    dfree(scratch);
+    scratch = nullptr;
+    scratch_stride = 0;
   }
   build_apply_jobs();
   HIPCHK(hipStreamSynchronize(s));
@@ -280,26 +297,54 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       if (k > 0) Acur[q][k] = Coupling{1, -1, probs[q].zA + (int64_t)k * B};
       if (k < nz - 1) Ccur[q][k] = Coupling{1, -1, probs[q].zC + (int64_t)k * B};
     }
-  // scratch instances of the H-inverse
-  std::vector<int> tpool;
+  // H-inverse of the given planes of every problem, in place, with scratch
+  // instances released right after; the inverses are final and get packed
   auto inverse_batch = [&](const std::vector<int>& planes) {
     const size_t nb = planes.size() * np;
+    std::vector<int> tpool;
     while (tpool.size() < nb) tpool.push_back(new_instance(s));
     std::vector<int32_t> roles;
+    std::vector<int> done;
     size_t b = 0;
     for (int q = 0; q < np; ++q)
       for (int pl : planes) {
         roles.push_back(probs[q].plane_inst[pl]);
         roles.push_back(tpool[b++]);
+        done.push_back(probs[q].plane_inst[pl]);
       }
     run_program(get_program("inv"), (int)nb, 2, roles, 0, {}, s);
+    for (int t : tpool) release_instance(t);
+    pack_instances(done, s);
+  };
+  // couplings created by this level are final once written
+  auto pack_new_couplings = [&](const std::vector<std::vector<Coupling>>& An,
+                                const std::vector<std::vector<Coupling>>& Cn) {
+    std::vector<int> ids;
+    for (int q = 0; q < np; ++q)
+      for (int k = 0; k < nz; ++k) {
+        if (An[q][k].kind == 2) ids.push_back(An[q][k].inst);
+        if (Cn[q][k].kind == 2) ids.push_back(Cn[q][k].inst);
+      }
+    pack_instances(ids, s);
   };
 
   std::vector<int> P(nz);
   for (int k = 0; k < nz; ++k) P[k] = k;
   int lev = 0;
+  const bool log = [] {
+    const char* e = getenv("ACR_LOG");
+    return e && e[0] == '1';
+  }();
+  const auto t_lev0 = std::chrono::steady_clock::now();
   while (true) {
     cur_level = lev;
+    if (log) {
+      HIPCHK(hipStreamSynchronize(s));
+      fprintf(stderr, "[acr] level %d: %zu planes, %.2f s, %.2f GB held (peak %.2f GB)\n", lev, P.size(),
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t_lev0).count(), bytes_alloc * 1e-9,
+              bytes_peak * 1e-9);
+      fflush(stderr);
+    }
     if (P.size() == 1) {
       inverse_batch(P);
       for (Prob& pr : probs) {
@@ -359,6 +404,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       }
       run_program(get_program("copy_schur"), (int)roles.size() / 3, 3, roles, 4, vecs, s);
       run_program(get_program("copy_direct"), (int)roles2.size() / 2, 2, roles2, 2, vecs2, s);
+      pack_new_couplings(An, Cn);
     } else {
       std::vector<int32_t> rXY, rS, rN;
       std::vector<int> tmp;
@@ -395,6 +441,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       run_program(get_program("mul_neg"), (int)rN.size() / 3, 3, rN, 0, {}, s);
       HIPCHK(hipStreamSynchronize(s));
       for (int t : tmp) release_instance(t);
+      pack_new_couplings(An, Cn);
     }
     for (int q = 0; q < np; ++q)
       for (int j : L.K) {
@@ -405,7 +452,6 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     ++lev;
   }
   HIPCHK(hipStreamSynchronize(s));
-  for (int t : tpool) release_instance(t);
 }
 
 // ------------------------------------------------------------ apply
@@ -563,6 +609,7 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.njobs = pj.n;
       a.inst_base = (float* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
+      a.inst_off = d_inst_off;
       a.coef = coef;
       a.seg_lo = d_seg_lo;
       a.rows_ptr = d_rows_ptr;
@@ -582,6 +629,7 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.njobs = pj.n;
       a.inst_base = (double* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
+      a.inst_off = d_inst_off;
       a.coef = coef;
       a.seg_lo = d_seg_lo;
       a.rows_ptr = d_rows_ptr;

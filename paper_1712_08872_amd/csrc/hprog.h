@@ -56,7 +56,8 @@ enum Flag : int32_t {
   FL_SINGULAR = 1,       // zero pivot in a dense leaf inverse
   FL_NONFINITE = 2,      // NaN/Inf met in a truncation
   FL_MAXRANK = 3,        // largest rank produced (atomicMax)
-  FL_COUNT = 4
+  FL_LAYOUT = 4,         // a packed (read-only) instance was addressed as a target
+  FL_COUNT = 5
 };
 
 template <typename T>
@@ -71,6 +72,7 @@ struct AccumArgs {
   const double* const* vec_ptr;  // [nbatch * nvroles] H-order plane vectors
   T* const* inst_base;         // [ninst]
   int32_t* const* inst_rank;   // [ninst] rank arrays (one entry per leaf)
+  const int64_t* const* inst_off;  // [ninst] packed per-leaf offsets (null: capacity layout)
   T* scratch;                  // per block slot: (max_m + max_n) * round width
   int64_t scratch_stride;
   double eps;
@@ -110,6 +112,7 @@ struct MvArgs {
   int32_t njobs;
   T* const* inst_base;
   int32_t* const* inst_rank;
+  const int64_t* const* inst_off;  // packed per-leaf offsets (every factor is packed)
   double* coef;               // [njobs * 2 * sstride]
   // segment -> leaves covering it (rows for N, columns for T)
   const int32_t* seg_lo;      // [nseg + 1] H-order bounds of leaf clusters

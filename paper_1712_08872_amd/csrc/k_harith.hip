@@ -50,6 +50,34 @@ __device__ __forceinline__ int rank_of(const AccumArgs<T>& A, int inst, int leaf
   return A.inst_rank[inst][leaf];
 }
 
+// Operand view of a stored leaf: dense data or the U / V factors with their
+// leading dimensions, in either the capacity layout (V after cap columns of
+// U) or the packed layout (exact rank, leading dimensions padded to 4).
+template <typename T>
+struct LeafRef {
+  const T* U;
+  const T* V;
+  int ldu, ldv;
+};
+
+template <typename T>
+__device__ __forceinline__ LeafRef<T> leaf_ref(const AccumArgs<T>& A, int inst, int leaf, const DLeaf& L) {
+  LeafRef<T> r;
+  const int64_t* po = A.inst_off[inst];
+  if (po) {
+    r.ldu = (L.m + 3) & ~3;
+    r.ldv = (L.n + 3) & ~3;
+    r.U = A.inst_base[inst] + po[leaf];
+    r.V = r.U + (int64_t)r.ldu * (L.fmt ? A.inst_rank[inst][leaf] : 0);
+  } else {
+    r.ldu = L.m;
+    r.ldv = L.n;
+    r.U = A.inst_base[inst] + L.off;
+    r.V = r.U + (int64_t)L.m * L.cap;
+  }
+  return r;
+}
+
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
@@ -535,13 +563,14 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
   if (P.kind == PK_LRX) {
     const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
     const DLeaf x = A.leaves[P.xleaf];
-    const T* Ux = leaf_base(A, xi, P.xleaf);
-    const T* Vx = Ux + (int64_t)x.m * x.cap;
+    const LeafRef<T> xr = leaf_ref(A, xi, P.xleaf, x);
+    const T* Ux = xr.U;
+    const T* Vx = xr.V;
     for (int idx = tid; idx < m * take; idx += TPB) {
       const int i = idx / take, jj = idx - i * take;
       const int gi = tc.r0 + i;
       const double v =
-          (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * x.m] : 0.0;
+          (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
@@ -556,12 +585,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int q0 = imax(lam.r0, x.c0), q1 = imin(lam.r0 + lam.m, x.c0 + x.n);
       if (cA >= cB || q0 >= q1) continue;
       const int nq = q1 - q0;
-      const T* lp = leaf_base(A, yi, l);
-      const T* vx = Vx + (q0 - x.c0) + (int64_t)j0 * x.n;
+      const LeafRef<T> lr = leaf_ref(A, yi, l, lam);
+      const T* lp = lr.U;
+      const T* vx = Vx + (q0 - x.c0) + (int64_t)j0 * xr.ldv;
       if (lam.fmt == 0) {
         for (int c0 = cA; c0 < cB; c0 += KC) {
           const int nc = imin(KC, cB - c0);
-          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lam.m, lam.m, vx, x.n, nq, nc, take, L.S0, L.S1,
+          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, L.S0, L.S1,
                      L.S2);
           FLOP(L, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
@@ -575,9 +605,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         const int kl = rank_of(A, yi, l);
         if (kl == 0) continue;
         const T* Ul = lp;
-        const T* Vl = lp + (int64_t)lam.m * lam.cap;
-        tn_product(Ul + (q0 - lam.r0), lam.m, vx, x.n, nq, kl, take, L.S0, L.S1, L.S2);
-        nn_acc(Vl + (cA - lam.c0), lam.n, cB - cA, kl, L.S0, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
+        const T* Vl = lr.V;
+        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, L.S0, L.S1, L.S2);
+        nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, L.S0, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
                L.S1);
         FLOP(L, 2.0 * kl * take * (nq + (cB - cA)));
       }
@@ -585,12 +615,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
   } else if (P.kind == PK_LRY) {
     const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
     const DLeaf y = A.leaves[P.yleaf];
-    const T* Uy = leaf_base(A, yi, P.yleaf);
-    const T* Vy = Uy + (int64_t)y.m * y.cap;
+    const LeafRef<T> yr = leaf_ref(A, yi, P.yleaf, y);
+    const T* Uy = yr.U;
+    const T* Vy = yr.V;
     for (int idx = tid; idx < n * take; idx += TPB) {
       const int c = idx / take, jj = idx - c * take;
       const int gc = tc.c0 + c;
-      const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * y.n] : 0.0;
+      const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
       Vs[(int64_t)c * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < m * take; idx += TPB) {
@@ -605,17 +636,18 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int q0 = imax(lam.c0, y.r0), q1 = imin(lam.c0 + lam.n, y.r0 + y.m);
       if (rA >= rB || q0 >= q1) continue;
       const int nq = q1 - q0;
-      const T* lp = leaf_base(A, xi, l);
-      const T* uy = Uy + (q0 - y.r0) + (int64_t)j0 * y.m;
+      const LeafRef<T> lr = leaf_ref(A, xi, l, lam);
+      const T* lp = lr.U;
+      const T* uy = Uy + (q0 - y.r0) + (int64_t)j0 * yr.ldu;
       if (lam.fmt == 0) {
         for (int qc = 0; qc < nq; qc += KC) {
           const int nqc = imin(KC, nq - qc);
           for (int idx = tid; idx < nqc * take; idx += TPB) {
             const int q = idx % nqc, jj = idx / nqc;
-            L.S0[q * KC + jj] = (double)uy[qc + q + (int64_t)jj * y.m];
+            L.S0[q * KC + jj] = (double)uy[qc + q + (int64_t)jj * yr.ldu];
           }
           __syncthreads();
-          nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lam.m, lam.m, rB - rA, nqc, L.S0, take,
+          nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, L.S0, take,
                  Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, L.S1);
           FLOP(L, 2.0 * (rB - rA) * nqc * take);
         }
@@ -623,9 +655,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         const int kl = rank_of(A, xi, l);
         if (kl == 0) continue;
         const T* Ul = lp;
-        const T* Vl = lp + (int64_t)lam.m * lam.cap;
-        tn_product(Vl + (q0 - lam.c0), lam.n, uy, y.m, nq, kl, take, L.S0, L.S1, L.S2);
-        nn_acc(Ul + (rA - lam.r0), lam.m, rB - rA, kl, L.S0, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
+        const T* Vl = lr.V;
+        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, L.S0, L.S1, L.S2);
+        nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, L.S0, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
                L.S1);
         FLOP(L, 2.0 * kl * take * (nq + (rB - rA)));
       }
@@ -634,8 +666,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     // dense product into a low-rank target: U-part = alpha P[:, cols], V-part = selector
     const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
     const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
-    const T* xp = leaf_base(A, xi, P.xleaf);
-    const T* yp = leaf_base(A, yi, P.yleaf);
+    const LeafRef<T> xr = leaf_ref(A, xi, P.xleaf, x), yr = leaf_ref(A, yi, P.yleaf, y);
+    const T* xp = xr.U;
+    const T* yp = yr.U;
     const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
     for (int idx = tid; idx < m * take; idx += TPB) {
       const int i = idx / take, jj = idx - i * take;
@@ -650,29 +683,30 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int nqc = imin(KC, M1 - qc);
       for (int idx = tid; idx < nqc * take; idx += TPB) {
         const int q = idx % nqc, jj = idx / nqc;
-        L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(P.wc0 + j0 + jj - y.c0) * y.m];
+        L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(P.wc0 + j0 + jj - y.c0) * yr.ldu];
       }
       __syncthreads();
-      nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, take,
+      nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, L.S0, take,
              Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, L.S1);
       FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * take);
     }
   } else {  // PK_COPY of a low-rank leaf
     const int si = inst_of(A, b, P.xrole);
     const DLeaf s = A.leaves[P.xleaf];
-    const T* Usrc = leaf_base(A, si, P.xleaf);
-    const T* Vsrc = Usrc + (int64_t)s.m * s.cap;
+    const LeafRef<T> sr = leaf_ref(A, si, P.xleaf, s);
+    const T* Usrc = sr.U;
+    const T* Vsrc = sr.V;
     const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
     const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
     for (int idx = tid; idx < m * take; idx += TPB) {
       const int i = idx / take, jj = idx - i * take;
-      double v = alpha * (double)Usrc[i + (int64_t)(j0 + jj) * s.m];
+      double v = alpha * (double)Usrc[i + (int64_t)(j0 + jj) * sr.ldu];
       if (rho) v *= rho[tc.r0 + i];
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
       const int c = idx / take, jj = idx - c * take;
-      double v = (double)Vsrc[c + (int64_t)(j0 + jj) * s.n];
+      double v = (double)Vsrc[c + (int64_t)(j0 + jj) * sr.ldv];
       if (gam) v *= gam[tc.c0 + c];
       Vs[(int64_t)c * KC + K + jj] = (T)v;
     }
@@ -723,8 +757,9 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
       if (xi < 0 || yi < 0) continue;
       const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
-      const T* xp = leaf_base(A, xi, P.xleaf);
-      const T* yp = leaf_base(A, yi, P.yleaf);
+      const LeafRef<T> xr = leaf_ref(A, xi, P.xleaf, x), yr = leaf_ref(A, yi, P.yleaf, y);
+      const T* xp = xr.U;
+      const T* yp = yr.U;
       const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
       for (int cc0 = P.wc0; cc0 < P.wc1; cc0 += KC) {
         const int nc = imin(KC, P.wc1 - cc0);
@@ -732,10 +767,10 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
           const int nqc = imin(KC, M1 - qc);
           for (int idx = tid; idx < nqc * nc; idx += TPB) {
             const int q = idx % nqc, jj = idx / nqc;
-            L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * y.m];
+            L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * yr.ldu];
           }
           __syncthreads();
-          nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * x.m, x.m, P.wr1 - P.wr0, nqc, L.S0, nc,
+          nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, L.S0, nc,
                  C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
           FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
         }
@@ -743,12 +778,13 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
     } else if (P.kind == PK_COPY && A.leaves[P.xleaf].fmt == 0) {
       const int si = inst_of(A, b, P.xrole);
       if (si < 0) continue;
-      const T* src = leaf_base(A, si, P.xleaf);
+      const LeafRef<T> sr = leaf_ref(A, si, P.xleaf, A.leaves[P.xleaf]);
+      const T* src = sr.U;
       const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
       const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
       for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
         int i = idx % tc.m, c = idx / tc.m;
-        double v = P.alpha * (double)src[idx];
+        double v = P.alpha * (double)src[i + (int64_t)c * sr.ldu];
         if (rho) v *= rho[tc.r0 + i];
         if (gam) v *= gam[tc.c0 + c];
         C[idx] = (T)((double)C[idx] + v);
@@ -767,12 +803,21 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
 }
 
 // ------------------------------------------------------------ main kernel
+// Narrow rounds leave LDS for three resident blocks per CU: hold the
+// register budget to that occupancy.
+#if KCV <= 40
+#define ACCUM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(3, 3)))
+#else
+// one block per CU (LDS): the whole register file, AGPRs included, is free
+#define ACCUM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(1, 1)))
+#endif
 template <typename T>
-__global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
+__global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T> A) {
   __shared__ Lds L;
   const int tid = threadIdx.x;
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
+  unsigned long long* prof = A.prof;
   if (tid == 0) L.flops = 0.0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
@@ -780,42 +825,36 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
     const int ci = inst_of(A, b, tg.crole);
     if (ci < 0) continue;
     const DLeaf tc = A.leaves[tg.cleaf];
-    T* C = leaf_base(A, ci, tg.cleaf);
-    T* Vs = Us + (int64_t)tc.m * KC;
-    unsigned long long* prof = A.prof;
-    PROF_ADD(PS_ITEMS, 1);
-    PROF_ADD(PS_NPIECES, tg.p1 - tg.p0);
-    const long long tdense0 = clock64();
-    if (tc.fmt == 0) {
-      // ---------------- dense target
-      if (!tg.beta)
-        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
-      __syncthreads();
-      dense_pieces(A, b, tg, tc, C, Us, Vs, L);
-      PROF_ADD(PS_DENSE, clock64() - tdense0);
+    if (A.inst_off[ci]) {  // targets are working instances (capacity layout)
+      if (tid == 0) atomicOr(&A.flags[FL_LAYOUT], 1);
       continue;
     }
-    // ---------------- low-rank target
+    T* C = leaf_base(A, ci, tg.cleaf);
+    T* Vs = Us + (int64_t)tc.m * KC;
+    PROF_ADD(PS_ITEMS, 1);
+    PROF_ADD(PS_NPIECES, tg.p1 - tg.p0);
+    const long long t_item = clock64();
+    const bool lr = tc.fmt != 0;
     int32_t* rk = &A.inst_rank[ci][tg.cleaf];
     T* Uc = C;
     T* Vc = C + (int64_t)tc.m * tc.cap;
-    if (tg.direct) {
+    if (lr && tg.direct) {  // exact scaled copy of a low-rank leaf
       const Piece P = A.pieces[tg.p0];
       const int si = inst_of(A, b, P.xrole);
       const int ks = si < 0 ? 0 : rank_of(A, si, P.xleaf);
-      const T* Usrc = si < 0 ? nullptr : leaf_base(A, si, P.xleaf);
-      const T* Vsrc = si < 0 ? nullptr : Usrc + (int64_t)tc.m * tc.cap;
+      LeafRef<T> sr{nullptr, nullptr, tc.m, tc.n};
+      if (si >= 0) sr = leaf_ref(A, si, P.xleaf, tc);
       const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
       const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
       for (int idx = tid; idx < tc.m * ks; idx += TPB) {
-        int i = idx % tc.m;
-        double v = P.alpha * (double)Usrc[idx];
+        int i = idx % tc.m, j = idx / tc.m;
+        double v = P.alpha * (double)sr.U[i + (int64_t)j * sr.ldu];
         if (rho) v *= rho[tc.r0 + i];
         Uc[idx] = (T)v;
       }
       for (int idx = tid; idx < tc.n * ks; idx += TPB) {
-        int c = idx % tc.n;
-        double v = (double)Vsrc[idx];
+        int c = idx % tc.n, j = idx / tc.n;
+        double v = (double)sr.V[c + (int64_t)j * sr.ldv];
         if (gam) v *= gam[tc.c0 + c];
         Vc[idx] = (T)v;
       }
@@ -823,36 +862,71 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
       __syncthreads();
       continue;
     }
-    int K = 0;
-    int kbase = 0;  // rank after the last recompression
-    const int k0 = tg.beta ? *rk : 0;
-    // Small targets that receive more columns than their smaller dimension
-    // are accumulated exactly as a dense m x n block and compressed once:
-    // fewer recompressions, and the sum is truncated only at the end.
+    const int k0 = (lr && tg.beta) ? *rk : 0;
+    // Small low-rank targets that receive more columns than their smaller
+    // dimension are accumulated exactly as a dense m x n block and
+    // compressed once: fewer recompressions, and the sum is truncated only
+    // at the end.
     if (tid == 0) L.ival[5] = 0;
     __syncthreads();
-    if (tc.m * tc.n <= DACC_MAX)
+    if (lr && tc.m * tc.n <= DACC_MAX)
       for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&L.ival[5], piece_width(A, b, A.pieces[p]));
     __syncthreads();
-    const bool dacc = tc.m * tc.n <= DACC_MAX && L.ival[5] > imin(tc.m, tc.n);
-    if (dacc) {
-      T* D = Us + (int64_t)(tc.m + tc.n) * KC;  // m x n, column-major
-      for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
-        const int i = idx % tc.m, c = idx / tc.m;
-        double v = 0.0;
-        for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
-        D[idx] = (T)v;
+    const bool dacc = lr && tc.m * tc.n <= DACC_MAX && L.ival[5] > imin(tc.m, tc.n);
+    T* D = lr ? Us + (int64_t)(tc.m + tc.n) * KC : C;  // dense accumulator, m x n column-major
+    if (!lr || dacc) {
+      if (lr) {
+        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+          const int i = idx % tc.m, c = idx / tc.m;
+          double v = 0.0;
+          for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
+          D[idx] = (T)v;
+        }
+        FLOP(L, 2.0 * tc.m * tc.n * k0);
+      } else if (!tg.beta) {
+        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) D[idx] = (T)0;
       }
-      FLOP(L, 2.0 * tc.m * tc.n * k0);
       __syncthreads();
-      const long long tp0 = clock64();
       dense_pieces(A, b, tg, tc, D, Us, Vs, L);
-      PROF_ADD(PS_PIECES_LR, clock64() - tp0);
-      // D = U V^T along the smaller dimension: rows (U = identity columns,
-      // V = rows of D) when m <= n, else columns (U = columns of D, V = identity)
-      const bool by_rows = tc.m <= tc.n;
-      const int sdim = by_rows ? tc.m : tc.n;
-      for (int j0 = 0; j0 < sdim;) {
+      if (!lr) {
+        PROF_ADD(PS_DENSE, clock64() - t_item);
+        continue;
+      }
+      PROF_ADD(PS_PIECES_LR, clock64() - t_item);
+    }
+    // ---------------- low-rank target: columns appended in rounds of ROUND
+    // beyond the current rank, recompressed in between (the cost of a
+    // recompression grows with the cube of its width).  The columns come
+    // from the pieces, or from the dense accumulator along its smaller
+    // dimension (rows when m <= n: U = identity columns, V = rows of D).
+    int K = 0;
+    int kbase = 0;  // rank after the last recompression
+    if (!dacc && tg.beta) {
+      for (int idx = tid; idx < tc.m * k0; idx += TPB) {
+        int i = idx % tc.m, j = idx / tc.m;
+        Us[(int64_t)i * KC + j] = Uc[idx];
+      }
+      for (int idx = tid; idx < tc.n * k0; idx += TPB) {
+        int c = idx % tc.n, j = idx / tc.n;
+        Vs[(int64_t)c * KC + j] = Vc[idx];
+      }
+      K = k0;
+      kbase = k0;
+      __syncthreads();
+    }
+    const bool by_rows = tc.m <= tc.n;
+    const int pend = dacc ? tg.p0 + 1 : tg.p1;
+    for (int p = tg.p0; p < pend; ++p) {
+      Piece P{};
+      int w;
+      if (dacc) {
+        w = by_rows ? tc.m : tc.n;
+      } else {
+        P = A.pieces[p];
+        w = piece_width(A, b, P);
+      }
+      int j0 = 0;
+      while (j0 < w) {
         const int klim = imin(KC, kbase + ROUND);
         if (K >= klim) {
           K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
@@ -862,59 +936,27 @@ __global__ __launch_bounds__(TPB) void accum_kernel(AccumArgs<T> A) {
           }
           kbase = K;
         }
-        const int take = imin(sdim - j0, imin(KC, kbase + ROUND) - K);
-        for (int idx = tid; idx < tc.m * take; idx += TPB) {
-          const int i = idx / take, jj = idx - i * take;
-          Us[(int64_t)i * KC + K + jj] = by_rows ? (T)(i == j0 + jj ? 1.0 : 0.0) : D[i + (int64_t)(j0 + jj) * tc.m];
+        const int take = imin(w - j0, imin(KC, kbase + ROUND) - K);
+        const long long tp0 = clock64();
+        if (dacc) {
+          for (int idx = tid; idx < tc.m * take; idx += TPB) {
+            const int i = idx / take, jj = idx - i * take;
+            Us[(int64_t)i * KC + K + jj] = by_rows ? (T)(i == j0 + jj ? 1.0 : 0.0) : D[i + (int64_t)(j0 + jj) * tc.m];
+          }
+          for (int idx = tid; idx < tc.n * take; idx += TPB) {
+            const int c = idx / take, jj = idx - c * take;
+            Vs[(int64_t)c * KC + K + jj] = by_rows ? D[(j0 + jj) + (int64_t)c * tc.m] : (T)(c == j0 + jj ? 1.0 : 0.0);
+          }
+          __syncthreads();
+        } else {
+          piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
         }
-        for (int idx = tid; idx < tc.n * take; idx += TPB) {
-          const int c = idx / take, jj = idx - c * take;
-          Vs[(int64_t)c * KC + K + jj] = by_rows ? D[(j0 + jj) + (int64_t)c * tc.m] : (T)(c == j0 + jj ? 1.0 : 0.0);
-        }
-        __syncthreads();
+        PROF_ADD(PS_PIECES_LR, clock64() - tp0);
         K += take;
         j0 += take;
       }
-    } else {
-      if (tg.beta) {
-        for (int idx = tid; idx < tc.m * k0; idx += TPB) {
-          int i = idx % tc.m, j = idx / tc.m;
-          Us[(int64_t)i * KC + j] = Uc[idx];
-        }
-        for (int idx = tid; idx < tc.n * k0; idx += TPB) {
-          int c = idx % tc.n, j = idx / tc.n;
-          Vs[(int64_t)c * KC + j] = Vc[idx];
-        }
-        K = k0;
-        kbase = k0;
-        __syncthreads();
-      }
-      for (int p = tg.p0; p < tg.p1; ++p) {
-        const Piece P = A.pieces[p];
-        const int w = piece_width(A, b, P);
-        int j0 = 0;
-        while (j0 < w) {
-          // recompress once ROUND columns have been appended beyond the current
-          // rank (the cost of a recompression grows with the cube of its width)
-          const int klim = imin(KC, kbase + ROUND);
-          if (K >= klim) {
-            K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
-            if (K > KC - 8) {
-              if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
-              K = KC - 8;
-            }
-            kbase = K;
-          }
-          int take = imin(w - j0, imin(KC, kbase + ROUND) - K);
-          const long long tp0 = clock64();
-          piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
-          PROF_ADD(PS_PIECES_LR, clock64() - tp0);
-          K += take;
-          j0 += take;
-        }
-      }
     }
-    if (tg.p1 > tg.p0 || !tg.beta) {
+    if (dacc || tg.p1 > tg.p0 || !tg.beta) {
       int k = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
       int kw = imin(k, tc.cap);
       if (tid == 0) {

@@ -39,6 +39,7 @@ void* Handle::dmalloc(size_t bytes) {
   }
   owned.emplace_back(p, bytes);
   bytes_alloc += bytes;
+  bytes_peak = std::max(bytes_peak, bytes_alloc);
   return p;
 }
 
@@ -69,10 +70,12 @@ Handle::~Handle() {
 }
 
 // ------------------------------------------------------------ instances
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 int Handle::new_instance(hipStream_t s) {
   const size_t esz = fp32 ? 4 : 8;
-  const size_t data = (size_t)G.inst_elems * esz;
-  const size_t bytes = ((data + 255) / 256) * 256 + G.lf.size() * sizeof(int32_t);
+  const size_t data = round_up((size_t)G.inst_elems * esz, 256);
+  const size_t bytes = data + G.lf.size() * sizeof(int32_t);
   int id;
   if (!free_inst.empty()) {
     id = free_inst.back();
@@ -80,21 +83,78 @@ int Handle::new_instance(hipStream_t s) {
   } else {
     id = (int)inst.size();
     inst.emplace_back();
-    Instance& I = inst[id];
-    I.base = dmalloc(bytes);
-    I.rank = (int32_t*)((char*)I.base + ((data + 255) / 256) * 256);
-    table_dirty = true;
   }
   Instance& I = inst[id];
+  if (!cap_pool.empty()) {
+    I.buf = cap_pool.back();
+    cap_pool.pop_back();
+  } else {
+    I.buf = dmalloc(bytes);
+  }
+  I.base = I.buf;
+  I.rank = (int32_t*)((char*)I.buf + data);
+  I.off = nullptr;
   I.live = true;
-  HIPCHK(hipMemsetAsync(I.base, 0, bytes, s));
+  I.packed = false;
+  I.packed_bytes = 0;
+  table_dirty = true;
+  HIPCHK(hipMemsetAsync(I.buf, 0, bytes, s));
   return id;
 }
 
 void Handle::release_instance(int id) {
-  if (id < 0) return;
-  inst[id].live = false;
+  if (id < 0 || !inst[id].live) return;
+  Instance& I = inst[id];
+  if (I.packed)
+    dfree(I.buf);
+  else
+    cap_pool.push_back(I.buf);
+  I = Instance{};
   free_inst.push_back(id);
+  table_dirty = true;
+}
+
+// Pack final instances: exact ranks, leading dimensions padded to 4
+// elements, per-leaf offsets; their capacity buffers return to the pool.
+void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
+  if (ids.empty()) return;
+  HIPCHK(hipStreamSynchronize(s));
+  const size_t esz = fp32 ? 4 : 8;
+  const size_t nl = G.lf.size();
+  std::vector<int32_t> rk(nl);
+  std::vector<int64_t> off(nl);
+  for (int id : ids) {
+    Instance& I = inst[id];
+    if (!I.live || I.packed) continue;
+    HIPCHK(hipMemcpy(rk.data(), I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int64_t acc = 0;
+    for (size_t l = 0; l < nl; ++l) {
+      const Leaf& L = G.lf[l];
+      off[l] = acc;
+      const int64_t ldm = (L.m + 3) & ~3, ldn = (L.n + 3) & ~3;
+      acc += L.fmt == LF_DENSE ? ldm * L.n : (ldm + ldn) * rk[l];
+    }
+    const size_t data = round_up((size_t)acc * esz, 256);
+    const size_t rbytes = round_up(nl * sizeof(int32_t), 256);
+    char* nb = (char*)dmalloc(data + rbytes + nl * sizeof(int64_t));
+    int32_t* nrank = (int32_t*)(nb + data);
+    int64_t* noff = (int64_t*)(nb + data + rbytes);
+    HIPCHK(hipMemcpy(noff, off.data(), nl * sizeof(int64_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(nrank, I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (fp32)
+      launch_pack<float>((const float*)I.base, I.rank, d_leaves, (int)nl, (float*)nb, noff, s);
+    else
+      launch_pack<double>((const double*)I.base, I.rank, d_leaves, (int)nl, (double*)nb, noff, s);
+    cap_pool.push_back(I.buf);  // later users are ordered after the pack on the stream
+    I.buf = nb;
+    I.base = nb;
+    I.rank = nrank;
+    I.off = noff;
+    I.packed = true;
+    I.packed_bytes = (double)acc * esz;
+  }
+  HIPCHK(hipGetLastError());
+  table_dirty = true;
 }
 
 void Handle::sync_tables() {
@@ -102,18 +162,23 @@ void Handle::sync_tables() {
   if ((int)inst.size() > inst_table_cap) {
     if (d_inst_base) dfree(d_inst_base);
     if (d_inst_rank) dfree(d_inst_rank);
+    if (d_inst_off) dfree(d_inst_off);
     inst_table_cap = std::max<int>(256, (int)inst.size() * 2);
     d_inst_base = dnew<void*>(inst_table_cap);
     d_inst_rank = dnew<int32_t*>(inst_table_cap);
+    d_inst_off = dnew<int64_t*>(inst_table_cap);
   }
   std::vector<void*> b(inst.size());
   std::vector<int32_t*> r(inst.size());
+  std::vector<int64_t*> o(inst.size());
   for (size_t i = 0; i < inst.size(); ++i) {
     b[i] = inst[i].base;
     r[i] = inst[i].rank;
+    o[i] = inst[i].off;
   }
   HIPCHK(hipMemcpy(d_inst_base, b.data(), b.size() * sizeof(void*), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(d_inst_rank, r.data(), r.size() * sizeof(int32_t*), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_inst_off, o.data(), o.size() * sizeof(int64_t*), hipMemcpyHostToDevice));
   table_dirty = false;
 }
 
@@ -209,6 +274,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.vec_ptr = d_vecs;
       a.inst_base = (float* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
+      a.inst_off = d_inst_off;
       a.scratch = (float*)scratch;
       a.scratch_stride = scratch_stride;
       a.eps = opt.eps;
@@ -248,6 +314,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       a.vec_ptr = d_vecs;
       a.inst_base = (double* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
+      a.inst_off = d_inst_off;
       a.scratch = (double*)scratch;
       a.scratch_stride = scratch_stride;
       a.eps = opt.eps;

@@ -44,6 +44,9 @@ void launch_level0(T* const*, const int32_t*, int nplanes, int plane0, const dou
 void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
                       hipStream_t);
 template <typename T> void launch_mv(const MvArgs<T>&, hipStream_t);
+template <typename T>
+void launch_pack(const T* src, const int32_t* rank, const DLeaf* leaves, int nleaf, T* dst, const int64_t* off,
+                 hipStream_t);
 void launch_assemble(int kind, int nx, int ny, int nz, const double* kappa, double ba, double bph, const double* c,
                      double omega, double* S, hipStream_t);
 void launch_stencil_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t);
@@ -62,11 +65,19 @@ void launch_lincomb(int64_t n, int nv, const double* V, int64_t ldv, const doubl
                     hipStream_t);
 void launch_check(const double* x, int64_t n, int positive, int32_t* flag, hipStream_t);
 
-// One stored or working H-matrix of a plane.
+// One stored or working H-matrix of a plane.  A working instance has the
+// capacity layout (every low-rank leaf holds `cap` columns at the leaf's
+// fixed offset); once it is final it is packed: exact ranks, leading
+// dimensions padded to a multiple of 4 elements, per-leaf offsets in a
+// device table.  Capacity buffers are recycled through a pool.
 struct Instance {
-  void* base = nullptr;      // inst_elems * sizeof(T) followed by nleaf int32 ranks
-  int32_t* rank = nullptr;
+  void* base = nullptr;      // leaf data (capacity or packed layout)
+  int32_t* rank = nullptr;   // device: one rank per leaf
+  int64_t* off = nullptr;    // device: per-leaf element offsets (packed); null = capacity layout
+  void* buf = nullptr;       // allocation holding data, ranks (and offsets)
   bool live = false;
+  bool packed = false;
+  double packed_bytes = 0;   // packed leaf data in bytes
 };
 
 struct Coupling {            // coupling of a plane to its previous (A) or next (C) plane
@@ -134,11 +145,15 @@ struct Handle {
   std::vector<Instance> inst;
   void** d_inst_base = nullptr;
   int32_t** d_inst_rank = nullptr;
+  int64_t** d_inst_off = nullptr;
+  std::vector<void*> cap_pool;          // free capacity-layout buffers
+  size_t bytes_peak = 0;
   int inst_table_cap = 0;
   bool table_dirty = true;
   std::vector<int> free_inst;
   int new_instance(hipStream_t s);
   void release_instance(int id);
+  void pack_instances(const std::vector<int>& ids, hipStream_t s);
   void sync_tables();
   // programs
   std::map<std::string, Program> prog;
