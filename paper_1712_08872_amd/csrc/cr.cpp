@@ -469,8 +469,10 @@ static MvTerm term_of(const Coupling& c, const double* x, double alpha, int tran
 
 void Handle::build_apply_jobs() {
   auto clear = [&](std::vector<PhaseJobs>& ph) {
-    for (auto& p : ph)
+    for (auto& p : ph) {
       if (p.d) dfree(p.d);
+      if (p.terms) dfree(p.terms);
+    }
     ph.clear();
   };
   clear(ph_apply);
@@ -571,6 +573,13 @@ void Handle::build_apply_jobs() {
       PhaseJobs pj;
       pj.d = upload(jobs);
       pj.n = (int)jobs.size();
+      std::vector<int32_t> terms;
+      for (size_t jj = 0; jj < jobs.size(); ++jj)
+        for (int tt = 0; tt < 2; ++tt)
+          if (jobs[jj].t[tt].inst >= 0) terms.push_back((int32_t)(2 * jj + tt));
+      pj.terms = upload(terms);
+      pj.nterms = (int)terms.size();
+      pj.trans = tr;
       max_jobs = std::max(max_jobs, pj.n);
       out.push_back(pj);
     }
@@ -584,6 +593,15 @@ void Handle::build_apply_jobs() {
     }
   if (coef) dfree(coef);
   coef = dnew<double>((size_t)std::max(max_jobs, 1) * 2 * sstride);
+}
+
+// Low-rank leaves per wavefront of the coefficient kernel: enough
+// wavefronts to fill the chip (~12k), at most 64 leaves each.
+static int coef_chunk(int nterms, int nlr) {
+  const int64_t work = (int64_t)nterms * nlr;
+  int c = 1;
+  while (c < 64 && work / (2 * c) >= 12288) c *= 2;
+  return c;
 }
 
 void Handle::apply(const std::vector<const double*>& r, const std::vector<double*>& out, bool transpose, int prob,
@@ -607,6 +625,10 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.sstride = sstride;
       a.jobs = pj.d;
       a.njobs = pj.n;
+      a.terms = pj.terms;
+      a.nterms = pj.nterms;
+      a.trans = pj.trans;
+      a.chunk = coef_chunk(pj.nterms, G.nlr);
       a.inst_base = (float* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
       a.inst_off = d_inst_off;
@@ -627,6 +649,10 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.sstride = sstride;
       a.jobs = pj.d;
       a.njobs = pj.n;
+      a.terms = pj.terms;
+      a.nterms = pj.nterms;
+      a.trans = pj.trans;
+      a.chunk = coef_chunk(pj.nterms, G.nlr);
       a.inst_base = (double* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
       a.inst_off = d_inst_off;

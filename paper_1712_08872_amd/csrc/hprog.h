@@ -110,6 +110,10 @@ struct MvArgs {
   int64_t sstride;            // per (job, term) coefficient stride
   const MvJob* jobs;
   int32_t njobs;
+  const int32_t* terms;       // non-empty H-matrix terms of the phase: 2 * job + term
+  int32_t nterms;
+  int32_t trans;              // 1: every term of the phase is transposed
+  int32_t chunk;              // low-rank leaves per wavefront in the coefficient kernel (<= 64)
   T* const* inst_base;
   int32_t* const* inst_rank;
   const int64_t* const* inst_off;  // packed per-leaf offsets (every factor is packed)

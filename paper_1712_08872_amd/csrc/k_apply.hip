@@ -6,13 +6,16 @@
 // stored H-matrix (Dinv_i or a coupling).  A *job* computes
 //     y = base + sum_t alpha_t op_t(H_t) x_t
 // for one plane, with up to two terms (op = identity or transpose; a term
-// may also be a diagonal vector, the level-0 z-couplings).  Two kernels:
-//   mv_lr_kernel   : s = V^T x_s (or U^T x_t) for every low-rank leaf, one
-//                    wavefront per rank column, coalesced over the leaf rows;
-//   mv_seg_kernel  : one block per (job, leaf cluster of the output): streams
-//                    the dense leaves and the U (or V) rows covering that
-//                    cluster once, reduces in registers + LDS.
-// Everything is FP64 except the factor loads (T = float in mixed mode).
+// may also be a diagonal vector, the level-0 z-couplings).  Every stored
+// H-matrix is packed (exact ranks, leading dimensions padded to a multiple
+// of 4 elements, leaves 4-element aligned), so columns stream with 16-byte
+// loads.  Three wavefront-level kernels, no block barriers:
+//   mv_coef_kernel : s = V^T x (or U^T x) per (job term, low-rank leaf);
+//                    a power-of-two group of lanes per column;
+//   mv_rows_kernel : y = sum D x + sum U s per (job, row segment);
+//   mv_cols_kernel : y = sum D^T x + sum V s per (job, column segment).
+// Sums are formed in a fixed order (deterministic results).  Arithmetic is
+// FP64; the factor loads are FP32 in mixed precision.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -21,110 +24,296 @@
 
 namespace acr {
 
+__device__ __forceinline__ int pad4(int x) { return (x + 3) & ~3; }
+__device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
+
+// Four consecutive elements (16-byte aligned for float, 32 for double).
+__device__ __forceinline__ void load4(const float* p, double* o) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double* o) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+
+// lanes per column: the power of two covering ceil(len / 4) quads, <= 64
+__device__ __forceinline__ int lanes_per_col(int len) {
+  int g = 1;
+  while (g * 4 < len && g < 64) g <<= 1;
+  return g;
+}
+
+// Uniform copies of lane i's value (the descriptors of a chunk of leaves
+// are fetched lane-parallel, then walked one leaf at a time).
+__device__ __forceinline__ int bcast(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, i);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), i);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// One wavefront per (job term, chunk of A.chunk consecutive low-rank leaves).
 template <typename T>
-__global__ __launch_bounds__(256) void mv_lr_kernel(MvArgs<T> A) {
+__global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t total = (int64_t)A.njobs * 2 * A.nlr;
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    const int jt = (int)(item / A.nlr);
-    const int li = (int)(item - (int64_t)jt * A.nlr);
-    const MvJob& J = A.jobs[jt >> 1];
-    const MvTerm& tm = J.t[jt & 1];
-    if (tm.inst < 0) continue;
-    const int l = A.lr_leaves[li];
-    const DLeaf L = A.leaves[l];
-    const int k = A.inst_rank[tm.inst][l];
-    const int ldu = (L.m + 3) & ~3, ldv = (L.n + 3) & ~3;
-    const T* U = A.inst_base[tm.inst] + A.inst_off[tm.inst][l];
-    const T* V = U + (int64_t)ldu * k;
-    double* out = A.coef + (int64_t)jt * A.sstride + A.soff[l];
-    // transposed: s = U^T x[t]; otherwise s = V^T x[s]
-    const T* F = tm.trans ? U : V;
-    const int len = tm.trans ? L.m : L.n;
-    const int ld = tm.trans ? ldu : ldv;
-    const double* x = tm.x + (tm.trans ? L.r0 : L.c0);
-    for (int a = wave; a < k; a += 4) {
-      const T* f = F + (int64_t)a * ld;
-      double s = 0.0;
-      for (int i = lane; i < len; i += 64) s += (double)f[i] * x[i];
+  const int nch = (A.nlr + A.chunk - 1) / A.chunk;
+  const int64_t nitems = (int64_t)A.nterms * nch;
+  for (int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); item < nitems; item += (int64_t)gridDim.x * 4) {
+    const int ti = (int)(item / nch);
+    const int li0 = (int)(item - (int64_t)ti * nch) * A.chunk;
+    const int cnt = imin_(A.chunk, A.nlr - li0);
+    const int jt = A.terms[ti];
+    const MvTerm& tm = A.jobs[jt >> 1].t[jt & 1];
+    const T* base = A.inst_base[tm.inst];
+    double* coef = A.coef + (int64_t)jt * A.sstride;
+    // lane-parallel descriptors
+    int dlen = 0, dld = 0, dk = 0, dx = 0;
+    int64_t doff = 0, dso = 0;
+    if (lane < cnt) {
+      const int l = A.lr_leaves[li0 + lane];
+      const DLeaf L = A.leaves[l];
+      dk = A.inst_rank[tm.inst][l];
+      const int ldu = pad4(L.m), ldv = pad4(L.n);
+      // transposed: s = U^T x[rows]; otherwise s = V^T x[cols]
+      doff = A.inst_off[tm.inst][l] + (A.trans ? 0 : (int64_t)ldu * dk);
+      dlen = A.trans ? L.m : L.n;
+      dld = A.trans ? ldu : ldv;
+      dx = A.trans ? L.r0 : L.c0;
+      dso = A.soff[l];
+    }
+    for (int i = 0; i < cnt; ++i) {
+      const int k = bcast(dk, i);
+      if (k == 0) continue;
+      const int len = bcast(dlen, i), ld = bcast(dld, i);
+      const T* F = base + bcast64(doff, i);
+      const double* x = tm.x + bcast(dx, i);
+      double* out = coef + bcast64(dso, i);
+      const int g = lanes_per_col(len), cpp = 64 / g;
+      const int q = lane & (g - 1), co = lane / g;
+      for (int a0 = 0; a0 < k; a0 += cpp) {
+        const int a = a0 + co;
+        double s = 0.0;
+        if (a < k) {
+          const T* f = F + (int64_t)a * ld;
+#pragma unroll 4
+          for (int r = 4 * q; r < len; r += 4 * g) {
+            double v[4];
+            load4(f + r, v);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      if (lane == 0) out[a] = s;
+            for (int e = 0; e < 4; ++e)
+              if (r + e < len) s += v[e] * x[r + e];
+          }
+        }
+        for (int o = g >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (q == 0 && a < k) out[a] = s;
+      }
     }
   }
 }
 
+// Lane-parallel descriptors of up to 64 leaves of a segment list.
+struct SegDesc {
+  int m, n, r0, c0, fmt, k;
+  int64_t off, so;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void mv_seg_kernel(MvArgs<T> A) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
-  const int64_t total = (int64_t)A.njobs * A.nseg;
-  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+__device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* idx, int e, int inst) {
+  SegDesc d;
+  const int l = idx[e];
+  const DLeaf L = A.leaves[l];
+  d.m = L.m;
+  d.n = L.n;
+  d.r0 = L.r0;
+  d.c0 = L.c0;
+  d.fmt = L.fmt;
+  d.k = L.fmt ? A.inst_rank[inst][l] : 0;
+  d.off = A.inst_off[inst][l];
+  d.so = L.fmt ? A.soff[l] : 0;
+  return d;
+}
+
+// y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi], one block per (job, row
+// segment); wavefront w takes every 4th leaf of the segment's list and the
+// four partial sums are added in wave order (deterministic).  Dense leaves:
+// lanes map to (row quad, column), 16-byte loads when the segment starts
+// 4-aligned inside the leaf; low-rank leaves: lane = row of U.
+template <typename T>
+__global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
+  __shared__ double red[4][256];
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* rw = red[w];
+  const int64_t nitems = (int64_t)A.njobs * A.nseg;
+  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int j = (int)(item / A.nseg);
     const int sg = (int)(item - (int64_t)j * A.nseg);
     const MvJob& J = A.jobs[j];
-    const int lo = A.seg_lo[sg], hi = A.seg_lo[sg + 1];
-    const int R = hi - lo;                 // rows of this segment (<= 64)
-    const int G = 256 / 64;                // column groups
-    const int r = tid & 63, g = tid >> 6;
-    double acc = 0.0;
+    const int lo = A.seg_lo[sg], R = A.seg_lo[sg + 1] - lo;  // R <= 64
+    const int ldR = pad4(R), g = ldR / 4, cpp = 64 / g;       // quad layout: g lanes per column
+    const int q = lane % g, co = lane / g;
+    const bool qact = co < cpp;
+    const int e0 = A.rows_ptr[sg], ne = A.rows_ptr[sg + 1] - e0;
+    double accq[4] = {0.0, 0.0, 0.0, 0.0};  // rows 4q..4q+3, column group co
+    double accr = 0.0;                      // row `lane` (low-rank part, diagonal terms)
     for (int tt = 0; tt < 2; ++tt) {
       const MvTerm& tm = J.t[tt];
       if (tm.inst < 0) {
-        if (tm.dvec && g == 0 && r < R) acc += tm.alpha * tm.dvec[lo + r] * tm.x[lo + r];
+        if (tm.dvec && w == 0 && lane < R) accr += tm.alpha * tm.dvec[lo + lane] * tm.x[lo + lane];
         continue;
       }
       const T* base = A.inst_base[tm.inst];
-      const int32_t* rk = A.inst_rank[tm.inst];
-      const int64_t* po = A.inst_off[tm.inst];
       const double* coef = A.coef + (int64_t)(2 * j + tt) * A.sstride;
-      double part = 0.0;
-      if (!tm.trans) {
-        for (int e = A.rows_ptr[sg]; e < A.rows_ptr[sg + 1]; ++e) {
-          const int l = A.rows_idx[e];
-          const DLeaf L = A.leaves[l];
-          const T* P = base + po[l];
-          const int ldm = (L.m + 3) & ~3;
-          if (r >= R) continue;
-          const int i = lo - L.r0 + r;
-          if (L.fmt == 0) {
-            const double* x = tm.x + L.c0;
-            for (int c = g; c < L.n; c += G) part += (double)P[i + (int64_t)c * ldm] * x[c];
+      const double al = tm.alpha;
+      for (int eb = w; eb < ne; eb += 256) {
+        const int cnt = imin_(64, (ne - eb + 3) / 4);  // this wave's leaves eb, eb+4, ...
+        SegDesc d{};
+        if (lane < cnt) d = seg_desc(A, A.rows_idx, e0 + eb + 4 * lane, tm.inst);
+        for (int i = 0; i < cnt; ++i) {
+          const int m = bcast(d.m, i), n = bcast(d.n, i), fmt = bcast(d.fmt, i);
+          const T* P = base + bcast64(d.off, i);
+          const int ro = lo - bcast(d.r0, i), ldm = pad4(m);
+          if (fmt == 0) {
+            const double* x = tm.x + bcast(d.c0, i);
+            if (!qact) continue;
+            if ((ro & 3) == 0) {
+#pragma unroll 4
+              for (int c = co; c < n; c += cpp) {
+                double v[4];
+                load4(P + (int64_t)c * ldm + ro + 4 * q, v);
+                const double xc = al * x[c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) accq[r] += v[r] * xc;
+              }
+            } else {
+#pragma unroll 4
+              for (int c = co; c < n; c += cpp) {
+                const T* col = P + (int64_t)c * ldm + ro + 4 * q;
+                const double xc = al * x[c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (4 * q + r < R) accq[r] += (double)col[r] * xc;
+              }
+            }
           } else {
-            const int k = rk[l];
-            const double* s = coef + A.soff[l];
-            for (int a = g; a < k; a += G) part += (double)P[i + (int64_t)a * ldm] * s[a];
-          }
-        }
-      } else {
-        for (int e = A.cols_ptr[sg]; e < A.cols_ptr[sg + 1]; ++e) {
-          const int l = A.cols_idx[e];
-          const DLeaf L = A.leaves[l];
-          const T* P = base + po[l];
-          const int ldm = (L.m + 3) & ~3, ldn = (L.n + 3) & ~3;
-          if (r >= R) continue;
-          const int c = lo - L.c0 + r;
-          if (L.fmt == 0) {
-            const double* x = tm.x + L.r0;
-            const T* col = P + (int64_t)c * ldm;
-            for (int i = g; i < L.m; i += G) part += (double)col[i] * x[i];
-          } else {
-            const int k = rk[l];
-            const double* s = coef + A.soff[l];
-            const T* V = P + (int64_t)ldm * k;
-            for (int a = g; a < k; a += G) part += (double)V[c + (int64_t)a * ldn] * s[a];
+            const int k = bcast(d.k, i);
+            const double* s = coef + bcast64(d.so, i);
+            if (lane < R) {
+#pragma unroll 8
+              for (int a = 0; a < k; ++a) accr += (double)P[ro + lane + (int64_t)a * ldm] * (al * s[a]);
+            }
           }
         }
       }
-      acc += tm.alpha * part;
     }
-    red[tid] = acc;
+    // this wave's rows: its column groups in a fixed order
+    if (qact)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rw[co * ldR + 4 * q + r] = accq[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < R) {
+      double sum = accr;
+      for (int c = 0; c < cpp; ++c) sum += rw[c * ldR + lane];
+      part[w][lane] = sum;
+    }
     __syncthreads();
-    if (g == 0 && r < R) {
-      double s = red[r] + red[r + 64] + red[r + 128] + red[r + 192];
-      if (J.base) s += J.base[lo + r];
-      J.y[lo + r] = s;
+    if (w == 0 && lane < R) {
+      double sum = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+      if (J.base) sum += J.base[lo + lane];
+      J.y[lo + lane] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// y[lo:hi] (+)= sum_t alpha_t (H_t^T x_t)[lo:hi], one block per (job,
+// column segment), leaves split over the four wavefronts as above.  Dense
+// leaves: one aligned column dot product per lane group (16-byte loads);
+// low-rank leaves: lane = row of V (= output column).
+template <typename T>
+__global__ __launch_bounds__(256) void mv_cols_kernel(MvArgs<T> A) {
+  __shared__ double yacc[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* yw = yacc[w];
+  const int64_t nitems = (int64_t)A.njobs * A.nseg;
+  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int j = (int)(item / A.nseg);
+    const int sg = (int)(item - (int64_t)j * A.nseg);
+    const MvJob& J = A.jobs[j];
+    const int lo = A.seg_lo[sg], R = A.seg_lo[sg + 1] - lo;
+    const int e0 = A.cols_ptr[sg], ne = A.cols_ptr[sg + 1] - e0;
+    yw[lane] = 0.0;
+    double accr = 0.0;
+    for (int tt = 0; tt < 2; ++tt) {
+      const MvTerm& tm = J.t[tt];
+      if (tm.inst < 0) {
+        if (tm.dvec && w == 0 && lane < R) accr += tm.alpha * tm.dvec[lo + lane] * tm.x[lo + lane];
+        continue;
+      }
+      const T* base = A.inst_base[tm.inst];
+      const double* coef = A.coef + (int64_t)(2 * j + tt) * A.sstride;
+      const double al = tm.alpha;
+      for (int eb = w; eb < ne; eb += 256) {
+        const int cnt = imin_(64, (ne - eb + 3) / 4);
+        SegDesc d{};
+        if (lane < cnt) d = seg_desc(A, A.cols_idx, e0 + eb + 4 * lane, tm.inst);
+        for (int i = 0; i < cnt; ++i) {
+          const int m = bcast(d.m, i), n = bcast(d.n, i), fmt = bcast(d.fmt, i);
+          const T* P = base + bcast64(d.off, i);
+          const int co0 = lo - bcast(d.c0, i), ldm = pad4(m);
+          if (fmt == 0) {
+            const double* x = tm.x + bcast(d.r0, i);
+            const int g = lanes_per_col(m), cpp = 64 / g;
+            const int q = lane & (g - 1), cg = lane / g;
+            for (int c0 = 0; c0 < R; c0 += cpp) {
+              const int c = c0 + cg;
+              double s = 0.0;
+              if (c < R) {
+                const T* col = P + (int64_t)(co0 + c) * ldm;
+#pragma unroll 4
+                for (int r = 4 * q; r < m; r += 4 * g) {
+                  double v[4];
+                  load4(col + r, v);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e)
+                    if (r + e < m) s += v[e] * x[r + e];
+                }
+              }
+              for (int o = g >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+              if (q == 0 && c < R) yw[c] += al * s;
+            }
+          } else {
+            const int k = bcast(d.k, i);
+            const double* s = coef + bcast64(d.so, i);
+            const T* V = P + (int64_t)ldm * k;
+            const int ldn = pad4(n);
+            if (lane < R) {
+#pragma unroll 8
+              for (int a = 0; a < k; ++a) accr += (double)V[co0 + lane + (int64_t)a * ldn] * (al * s[a]);
+            }
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    yw[lane] += accr;
+    __syncthreads();
+    if (w == 0 && lane < R) {
+      double sum = yacc[0][lane] + yacc[1][lane] + yacc[2][lane] + yacc[3][lane];
+      if (J.base) sum += J.base[lo + lane];
+      J.y[lo + lane] = sum;
     }
     __syncthreads();
   }
@@ -175,12 +364,17 @@ template void launch_pack<float>(const float*, const int32_t*, const DLeaf*, int
 
 template <typename T>
 void launch_mv(const MvArgs<T>& a, hipStream_t s) {
-  int64_t n1 = (int64_t)a.njobs * 2 * a.nlr;
-  int g1 = (int)(n1 < 8192 ? n1 : 8192);
-  if (g1 > 0) hipLaunchKernelGGL(mv_lr_kernel<T>, dim3(g1), dim3(256), 0, s, a);
-  int64_t n2 = (int64_t)a.njobs * a.nseg;
-  int g2 = (int)(n2 < 8192 ? n2 : 8192);
-  if (g2 > 0) hipLaunchKernelGGL(mv_seg_kernel<T>, dim3(g2), dim3(256), 0, s, a);
+  const int64_t n1 = ((int64_t)a.nterms * ((a.nlr + a.chunk - 1) / a.chunk) + 3) / 4;
+  const int g1 = (int)(n1 < 16384 ? n1 : 16384);
+  if (g1 > 0) hipLaunchKernelGGL(mv_coef_kernel<T>, dim3(g1), dim3(256), 0, s, a);
+  const int64_t n2 = (int64_t)a.njobs * a.nseg;
+  const int g2 = (int)(n2 < 16384 ? n2 : 16384);
+  if (g2 > 0) {
+    if (a.trans)
+      hipLaunchKernelGGL(mv_cols_kernel<T>, dim3(g2), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(mv_rows_kernel<T>, dim3(g2), dim3(256), 0, s, a);
+  }
 }
 
 template void launch_mv<double>(const MvArgs<double>&, hipStream_t);

@@ -127,8 +127,18 @@ void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
     Instance& I = inst[id];
     if (!I.live || I.packed) continue;
     HIPCHK(hipMemcpy(rk.data(), I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    // storage order: by first row, then first column, so that the leaves
+    // a row segment of the matrix-vector product reads lie together
+    if (pack_order.size() != nl) {
+      pack_order.resize(nl);
+      for (size_t l = 0; l < nl; ++l) pack_order[l] = (int)l;
+      std::stable_sort(pack_order.begin(), pack_order.end(), [&](int a, int b) {
+        const Leaf &A = G.lf[a], &B = G.lf[b];
+        return A.r0 != B.r0 ? A.r0 < B.r0 : A.c0 < B.c0;
+      });
+    }
     int64_t acc = 0;
-    for (size_t l = 0; l < nl; ++l) {
+    for (int l : pack_order) {
       const Leaf& L = G.lf[l];
       off[l] = acc;
       const int64_t ldm = (L.m + 3) & ~3, ldn = (L.n + 3) & ~3;

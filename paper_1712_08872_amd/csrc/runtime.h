@@ -95,6 +95,9 @@ struct Level {
 struct PhaseJobs {           // device job array of one apply phase
   MvJob* d = nullptr;
   int n = 0;
+  int32_t* terms = nullptr;  // non-empty H-matrix terms (2 * job + term)
+  int nterms = 0;
+  int trans = 0;
 };
 
 // One problem of a handle.  All problems of a handle share the plane shape
@@ -147,6 +150,7 @@ struct Handle {
   int32_t** d_inst_rank = nullptr;
   int64_t** d_inst_off = nullptr;
   std::vector<void*> cap_pool;          // free capacity-layout buffers
+  std::vector<int> pack_order;          // storage order of the leaves in packed instances
   size_t bytes_peak = 0;
   int inst_table_cap = 0;
   bool table_dirty = true;
