@@ -12,5 +12,5 @@ node grid that includes the Dirichlet boundary layer, x fastest.
 from .fields import (  # noqa: F401
     gaussian_field_exp, kappa_lognormal, kappa_subcubes, rhs_uniform,
     helmholtz_velocity, helmholtz_omega, point_source, cd_phase,
-    config_inputs,
+    config_inputs, batched_problems,
 )

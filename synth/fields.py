@@ -115,6 +115,21 @@ def point_source(n):
     return f.reshape(-1)
 
 
+def batched_problems(count=48, sizes=(31, 47, 63)):
+    """Independent convection-diffusion problems of uneven size: problem i
+    draws n from ``sizes`` and its phase, ``kappa = exp(g)`` (lognormal
+    field) and ``f ~ U(-1, 1)`` from seed ``100 + i``; ``beta_amp = 100``.
+    Returns a list of dicts (n, kappa, beta_amp, beta_phase, f)."""
+    out = []
+    for i in range(count):
+        rng = _rng(100 + i)
+        n = int(sizes[int(rng.integers(len(sizes)))])
+        out.append(dict(n=n, kappa=np.exp(gaussian_field_exp((n + 2,) * 3, 100 + i)),
+                        beta_amp=100.0, beta_phase=float(rng.uniform(0.0, 2.0 * np.pi)),
+                        f=rhs_uniform(n ** 3, 100 + i)))
+    return out
+
+
 def config_inputs(name, seed_offset=0):
     """Inputs of the named workload as a dict of numpy arrays/scalars.
 
