@@ -99,7 +99,7 @@ struct Lds {
   double S2[KC * LDM];
   double S3[KC * LDM];
   double v0[KC], v1[KC];
-  int permU[KC], permV[KC], posU[KC], posV[KC], order[KC];
+  int permU[KC], permV[KC], posU[KC], posV[KC], order[KC], permC[KC], posC[KC];
   int ival[8];
   double dval[4];
   double flops;          // algorithmic flops of the current item (thread 0)
@@ -244,7 +244,7 @@ __device__ int wave_pivoted_cholesky(double* G, int K, int* perm, int* pos, doub
 
 // One-sided Jacobi (Hestenes) on the columns of C (rows x cols, LDS ld KC):
 // C <- C Z with orthogonal columns, Z accumulated (initialised by the
-// caller).  Column pairs in tournament order, one pair per group of 8 lanes
+// caller; Z may be null).  Column pairs in tournament order, one pair per group of 8 lanes
 // (up to 32 pairs per round across the block), dot products reduced with
 // lane shuffles, one barrier per round.  Pairs whose inner product is below
 // 1e-15 of the geometric mean of their norms, or below 1e-18 ||C||_F^2,
@@ -302,11 +302,12 @@ __device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sf
               C[i * LDM + p] = cs * x - sn * y;
               C[i * LDM + q] = sn * x + cs * y;
             }
-            for (int i = l; i < cols; i += 8) {
-              const double x = Z[i * LDM + p], y = Z[i * LDM + q];
-              Z[i * LDM + p] = cs * x - sn * y;
-              Z[i * LDM + q] = sn * x + cs * y;
-            }
+            if (Z)
+              for (int i = l; i < cols; i += 8) {
+                const double x = Z[i * LDM + p], y = Z[i * LDM + q];
+                Z[i * LDM + p] = cs * x - sn * y;
+                Z[i * LDM + q] = sn * x + cs * y;
+              }
             if (l == 0) *sflag = 1;
           }
         }
@@ -370,7 +371,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   long long t2 = clock64();
   PROF_ADD(PS_EIG1, t2 - t1);
   if (rU == 0 || rV == 0) return 0;
-  // core C = R_U P_U^T P_V R_V^T (rU x rV) -> S1 ; Z = I -> S3
+  // core C = R_U P_U^T P_V R_V^T (rU x rV) -> S1
   for (int idx = tid; idx < rU * rV; idx += TPB) {
     const int a = idx / rV, c = idx - a * rV;
     double s = 0.0;
@@ -380,25 +381,84 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     }
     L.S1[a * LDM + c] = s;
   }
-  for (int idx = tid; idx < rV * rV; idx += TPB) {
-    const int a = idx / rV, c = idx - a * rV;
-    L.S3[a * LDM + c] = (a == c) ? 1.0 : 0.0;
-  }
   __syncthreads();
-  const int sweeps = onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
+  FLOP(L, 2.0 * rU * rV * K);
+  // Rank pre-reduction of the core: Cholesky with symmetric pivoting of
+  // H = C^T C, stopped once every remaining diagonal entry is below
+  // (0.01 eps)^2 max diag(H).  The dropped part E of C then has
+  // ||E||_F <= sqrt(rV) 0.01 eps sigma_1, far below the truncation level,
+  // and C ~ Q M with M = R_C P_C^T (r' x rV).  The rotations act on the
+  // r' columns of M^T only: M^T W = Z S gives the right singular vectors
+  // Z and the singular values S, and C Z the left ones (times S).
+  constexpr int PER = (KC * KC + TPB - 1) / TPB;
+  const double ptol = 1e-4 * eps * eps;
+  int rr = rV;
+  bool reduced = false;
+  if (rV > 8 && ptol > 1e-15) {
+    for (int idx = tid; idx < rV * rV; idx += TPB) {
+      const int a = idx / rV, c = idx - a * rV;
+      double s = 0.0;
+      for (int i = 0; i < rU; ++i) s += L.S1[i * LDM + a] * L.S1[i * LDM + c];
+      L.S3[a * LDM + c] = s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int r = wave_pivoted_cholesky(L.S3, rV, L.permC, L.posC, ptol);
+      if (tid == 0) L.ival[6] = r;
+    }
+    __syncthreads();
+    const int rp = L.ival[6];
+    FLOP(L, (double)rU * rV * rV + (double)rV * rV * rp);
+    if (rp > 0 && rp + 3 <= rV) {
+      // M^T (rV x r'): row i is column pos_C(i) of the pivot-ordered R_C
+      double tmp[PER];
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int idx = tid + e * TPB;
+        tmp[e] = 0.0;
+        if (idx < rV * rp) {
+          const int i = idx / rp, a = idx - i * rp, pc = L.posC[i];
+          tmp[e] = pc >= a ? L.S3[a * LDM + pc] : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int idx = tid + e * TPB;
+        if (idx < rV * rp) {
+          const int i = idx / rp, a = idx - i * rp;
+          L.S3[i * LDM + a] = tmp[e];
+        }
+      }
+      __syncthreads();
+      reduced = true;
+      rr = rp;
+    }
+  }
+  if (!reduced) {  // Z = I -> S3
+    for (int idx = tid; idx < rV * rV; idx += TPB) {
+      const int a = idx / rV, c = idx - a * rV;
+      L.S3[a * LDM + c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+  }
+  const int sweeps = reduced ? onesided_jacobi(L.S3, nullptr, rV, rr, &L.ival[4], L.dval)
+                             : onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
   PROF_ADD(PS_SWEEPS, sweeps);
-  FLOP(L, 2.0 * rU * rV * K + (double)sweeps * (rV / 2) * (rV - 1 + (rV & 1)) * (12.0 * rU + 6.0 * rV));
-  // singular values = column norms of the rotated core; order, rank
-  if (tid < rV) {
+  const int jrows = reduced ? rV : rU;
+  FLOP(L, (double)sweeps * (rr / 2) * (rr - 1 + (rr & 1)) * (12.0 * jrows + (reduced ? 0.0 : 6.0 * rV)));
+  // singular values = column norms of the rotated matrix; order, rank
+  const double* Rot = reduced ? L.S3 : L.S1;
+  if (tid < rr) {
     double s = 0.0;
-    for (int i = 0; i < rU; ++i) s += L.S1[i * LDM + tid] * L.S1[i * LDM + tid];
+    for (int i = 0; i < jrows; ++i) s += Rot[i * LDM + tid] * Rot[i * LDM + tid];
     L.v1[tid] = sqrt(s);
   }
   __syncthreads();
-  if (tid < rV) {
+  if (tid < rr) {
     const double sa = L.v1[tid];
     int rnk = 0;
-    for (int b2 = 0; b2 < rV; ++b2) {
+    for (int b2 = 0; b2 < rr; ++b2) {
       const double sb = L.v1[b2];
       if (sb > sa || (sb == sa && b2 < tid)) ++rnk;
     }
@@ -409,11 +469,45 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     const double s1 = L.v1[L.order[0]];
     int k = 0;
     if (s1 > 0.0 && isfinite(s1))
-      while (k < rV && L.v1[L.order[k]] > eps * s1) ++k;
+      while (k < rr && L.v1[L.order[k]] > eps * s1) ++k;
     if (!isfinite(s1)) atomicOr(&flags[FL_NONFINITE], 1);
     L.ival[2] = k;
   }
   __syncthreads();
+  if (reduced) {
+    // right singular vectors: rotated columns / sigma (S3, rV rows); left
+    // ones times sigma: C Z -> the same columns of S1 (rU rows)
+    const int kk = L.ival[2];
+    for (int idx = tid; idx < rV * rr; idx += TPB) {
+      const int i = idx / rr, a = idx - i * rr;
+      const double sg = L.v1[a];
+      L.S3[i * LDM + a] = sg > 0.0 ? L.S3[i * LDM + a] / sg : 0.0;
+    }
+    __syncthreads();
+    double tmp[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + e * TPB;
+      tmp[e] = 0.0;
+      if (idx < rU * kk) {
+        const int i = idx / kk, a = L.order[idx - i * kk];
+        double s = 0.0;
+        for (int j = 0; j < rV; ++j) s += L.S1[i * LDM + j] * L.S3[j * LDM + a];
+        tmp[e] = s;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + e * TPB;
+      if (idx < rU * kk) {
+        const int i = idx / kk, a = L.order[idx - i * kk];
+        L.S1[i * LDM + a] = tmp[e];
+      }
+    }
+    __syncthreads();
+    FLOP(L, 2.0 * rU * rV * kk);
+  }
   const int k = L.ival[2];
   if (k == 0) return 0;
   // back substitution R_U11 y = C[:, order[c]] and R_V11 y = Z[:, order[c]],
