@@ -141,11 +141,41 @@ __device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* i
   return d;
 }
 
+// One (leaf, pass) unit of the row kernel for this lane: rows 4q..4q+3 of
+// the segment in column c of a dense leaf or of a U factor, and the weight
+// of that column (x[c] for a dense leaf, the coefficient s[c] for U).
+template <typename T>
+struct RowUnit {
+  double v[4];
+  double w;
+};
+
+template <typename T>
+__device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c, int ncols, const double* wp, int q,
+                                              int R, bool act, RowUnit<T>& u) {
+  if (act && c < ncols) {
+    const T* col = P + (int64_t)c * ldm + ro + 4 * q;
+    if ((ro & 3) == 0) {
+      load4(col, u.v);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) u.v[r] = (4 * q + r < R) ? (double)col[r] : 0.0;
+    }
+    u.w = wp[c];
+  } else {
+    u.v[0] = u.v[1] = u.v[2] = u.v[3] = 0.0;
+    u.w = 0.0;
+  }
+}
+
 // y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi], one block per (job, row
 // segment); wavefront w takes every 4th leaf of the segment's list and the
-// four partial sums are added in wave order (deterministic).  Dense leaves:
-// lanes map to (row quad, column), 16-byte loads when the segment starts
-// 4-aligned inside the leaf; low-rank leaves: lane = row of U.
+// four partial sums are added in wave order (deterministic).  A dense leaf
+// contributes its columns weighted by x, a low-rank leaf the columns of U
+// weighted by its coefficients s = V^T x; lanes map to (row quad, column)
+// with 16-byte loads when the segment starts 4-aligned inside the leaf.
+// The loads of the next (leaf, column pass) are issued before the current
+// one is accumulated.
 template <typename T>
 __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
   __shared__ double red[4][256];
@@ -163,7 +193,7 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
     const bool qact = co < cpp;
     const int e0 = A.rows_ptr[sg], ne = A.rows_ptr[sg + 1] - e0;
     double accq[4] = {0.0, 0.0, 0.0, 0.0};  // rows 4q..4q+3, column group co
-    double accr = 0.0;                      // row `lane` (low-rank part, diagonal terms)
+    double accr = 0.0;                      // row `lane` (diagonal terms)
     for (int tt = 0; tt < 2; ++tt) {
       const MvTerm& tm = J.t[tt];
       if (tm.inst < 0) {
@@ -177,40 +207,42 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
         const int cnt = imin_(64, (ne - eb + 3) / 4);  // this wave's leaves eb, eb+4, ...
         SegDesc d{};
         if (lane < cnt) d = seg_desc(A, A.rows_idx, e0 + eb + 4 * lane, tm.inst);
-        for (int i = 0; i < cnt; ++i) {
-          const int m = bcast(d.m, i), n = bcast(d.n, i), fmt = bcast(d.fmt, i);
-          const T* P = base + bcast64(d.off, i);
-          const int ro = lo - bcast(d.r0, i), ldm = pad4(m);
-          if (fmt == 0) {
-            const double* x = tm.x + bcast(d.c0, i);
-            if (!qact) continue;
-            if ((ro & 3) == 0) {
-#pragma unroll 4
-              for (int c = co; c < n; c += cpp) {
-                double v[4];
-                load4(P + (int64_t)c * ldm + ro + 4 * q, v);
-                const double xc = al * x[c];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) accq[r] += v[r] * xc;
-              }
-            } else {
-#pragma unroll 4
-              for (int c = co; c < n; c += cpp) {
-                const T* col = P + (int64_t)c * ldm + ro + 4 * q;
-                const double xc = al * x[c];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                  if (4 * q + r < R) accq[r] += (double)col[r] * xc;
-              }
-            }
-          } else {
-            const int k = bcast(d.k, i);
-            const double* s = coef + bcast64(d.so, i);
-            if (lane < R) {
-#pragma unroll 8
-              for (int a = 0; a < k; ++a) accr += (double)P[ro + lane + (int64_t)a * ldm] * (al * s[a]);
-            }
+        // walk the (leaf, column pass) units with one unit of prefetch
+        int i = 0, c0 = 0;
+        const T* P = nullptr;
+        const double* wp = nullptr;
+        int ldm = 0, ro = 0, ncols = 0;
+        auto leaf = [&](int ii) {
+          const int fmt = bcast(d.fmt, ii);
+          P = base + bcast64(d.off, ii);
+          ldm = pad4(bcast(d.m, ii));
+          ro = lo - bcast(d.r0, ii);
+          ncols = fmt ? bcast(d.k, ii) : bcast(d.n, ii);
+          wp = fmt ? coef + bcast64(d.so, ii) : tm.x + bcast(d.c0, ii);
+        };
+        if (cnt == 0) continue;
+        leaf(0);
+        RowUnit<T> cur, nxt;
+        row_unit_load(P, ldm, ro, co, ncols, wp, q, R, qact, cur);
+        while (true) {
+          // advance to the next unit
+          int ni = i, nc0 = c0 + cpp;
+          if (nc0 >= ncols) {
+            ni = i + 1;
+            nc0 = 0;
           }
+          const bool more = ni < cnt;
+          if (more) {
+            if (ni != i) leaf(ni);
+            row_unit_load(P, ldm, ro, nc0 + co, ncols, wp, q, R, qact, nxt);
+          }
+          const double wc = al * cur.w;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accq[r] += cur.v[r] * wc;
+          if (!more) break;
+          cur = nxt;
+          i = ni;
+          c0 = nc0;
         }
       }
     }

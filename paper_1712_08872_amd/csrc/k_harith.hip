@@ -654,6 +654,8 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
   const int tid = threadIdx.x;
   const int m = tc.m, n = tc.n;
   const double alpha = P.alpha;
+  unsigned long long* prof = A.prof;
+  const long long tpc = clock64();
   if (P.kind == PK_LRX) {
     const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
     const DLeaf x = A.leaves[P.xleaf];
@@ -806,6 +808,8 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     }
   }
   __syncthreads();
+  if (P.kind == PK_LRX) PROF_ADD(PS_LRX, clock64() - tpc);
+  if (P.kind == PK_LRY) PROF_ADD(PS_LRY, clock64() - tpc);
 }
 
 // Dense target: C += Us Vs^T for `take` columns (C column-major m x n).
@@ -845,8 +849,10 @@ template <typename T>
 __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
                              Lds& L) {
   const int tid = threadIdx.x;
+  unsigned long long* prof = A.prof;
   for (int p = tg.p0; p < tg.p1; ++p) {
     const Piece P = A.pieces[p];
+    const long long tpd = clock64();
     if (P.kind == PK_DD) {
       const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
       if (xi < 0 || yi < 0) continue;
@@ -869,6 +875,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
           FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
         }
       }
+      PROF_ADD(PS_DDP, clock64() - tpd);
     } else if (P.kind == PK_COPY && A.leaves[P.xleaf].fmt == 0) {
       const int si = inst_of(A, b, P.xrole);
       if (si < 0) continue;
@@ -889,7 +896,9 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       for (int j0 = 0; j0 < w; j0 += KC) {
         int take = imin(KC, w - j0);
         piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
+        const long long to = clock64();
         dense_add_outer(C, tc, Us, Vs, take, L);
+        PROF_ADD(PS_OUTER, clock64() - to);
         FLOP(L, 2.0 * tc.m * tc.n * take);
       }
     }
@@ -986,7 +995,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
         PROF_ADD(PS_DENSE, clock64() - t_item);
         continue;
       }
-      PROF_ADD(PS_PIECES_LR, clock64() - t_item);
+      PROF_ADD(PS_DACC, clock64() - t_item);
     }
     // ---------------- low-rank target: columns appended in rounds of ROUND
     // beyond the current rank, recompressed in between (the cost of a
