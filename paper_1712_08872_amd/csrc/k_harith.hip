@@ -644,6 +644,154 @@ __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const double* Z,
   }
 }
 
+// One-leaf list whose overlap with the piece fits one staging tile: the
+// product is formed in one LDS round and its rows are written directly.
+//   LRX: U part = alpha U_x (window rows); V part on the window columns =
+//        lam^T V_x, i.e. V_l (U_l^T V_x) for a low-rank lam.
+//   LRY: V part = V_y (window columns); U part on the window rows =
+//        alpha lam U_y, i.e. alpha U_l (V_l^T U_y) for a low-rank lam.
+// Returns false when the piece does not qualify (the general path runs).
+template <typename T>
+__device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& x,
+                           const LeafRef<T>& xr, int yi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+  if (P.l1 - P.l0 != 1) return false;
+  const int l = A.lists[P.l0];
+  const DLeaf lam = A.leaves[l];
+  const int cA = imax(lam.c0, P.wc0), cB = imin(lam.c0 + lam.n, P.wc1);
+  const int q0 = imax(lam.r0, x.c0), q1 = imin(lam.r0 + lam.m, x.c0 + x.n);
+  const int nq = q1 - q0, nc = cB - cA;
+  const int kl = lam.fmt ? rank_of(A, yi, l) : 0;
+  if (nq <= 0 || nq > KC || nc <= 0 || (lam.fmt ? kl > KC : nc > KC)) return false;
+  const int tid = threadIdx.x;
+  const int m = tc.m, n = tc.n;
+  const double alpha = P.alpha;
+  const LeafRef<T> lr = leaf_ref(A, yi, l, lam);
+  const T* vx = xr.V + (q0 - x.c0) + (int64_t)j0 * xr.ldv;
+  for (int idx = tid; idx < m * take; idx += TPB) {
+    const int i = idx / take, jj = idx - i * take;
+    const int gi = tc.r0 + i;
+    const double v =
+        (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)xr.U[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
+    Us[(int64_t)i * KC + K + jj] = (T)v;
+  }
+  for (int idx = tid; idx < n * take; idx += TPB) {
+    const int c = idx / take, jj = idx - c * take;
+    const int gc = tc.c0 + c;
+    if (gc < cA || gc >= cB) Vs[(int64_t)c * KC + K + jj] = (T)0;
+  }
+  for (int idx = tid; idx < nq * take; idx += TPB) {
+    const int q = idx % nq, jj = idx / nq;
+    L.S2[q * KC + jj] = (double)vx[q + (int64_t)jj * xr.ldv];
+  }
+  if (lam.fmt) {
+    for (int idx = tid; idx < nq * kl; idx += TPB) {
+      const int q = idx % nq, a = idx / nq;
+      L.S1[q * KC + a] = (double)lr.U[(q0 - lam.r0) + q + (int64_t)a * lr.ldu];
+    }
+  } else {
+    for (int idx = tid; idx < nq * nc; idx += TPB) {
+      const int q = idx % nq, cc = idx / nq;
+      L.S1[q * KC + cc] = (double)lr.U[(q0 - lam.r0) + q + (int64_t)(cA - lam.c0 + cc) * lr.ldu];
+    }
+  }
+  __syncthreads();
+  if (lam.fmt) {
+    for (int idx = tid; idx < kl * take; idx += TPB) {
+      const int a = idx / take, jj = idx - a * take;
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + a] * L.S2[q * KC + jj];
+      L.S0[a * KC + jj] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nc * take; idx += TPB) {
+      const int cc = idx / take, jj = idx - cc * take;
+      double s = 0.0;
+      for (int a = 0; a < kl; ++a) s += (double)lr.V[(cA - lam.c0 + cc) + (int64_t)a * lr.ldv] * L.S0[a * KC + jj];
+      Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
+    }
+    FLOP(L, 2.0 * kl * take * (nq + nc));
+  } else {
+    for (int idx = tid; idx < nc * take; idx += TPB) {
+      const int cc = idx / take, jj = idx - cc * take;
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + cc] * L.S2[q * KC + jj];
+      Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
+    }
+    FLOP(L, 2.0 * nq * nc * take);
+  }
+  return true;
+}
+
+template <typename T>
+__device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& y,
+                           const LeafRef<T>& yr, int xi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+  if (P.l1 - P.l0 != 1) return false;
+  const int l = A.lists[P.l0];
+  const DLeaf lam = A.leaves[l];
+  const int rA = imax(lam.r0, P.wr0), rB = imin(lam.r0 + lam.m, P.wr1);
+  const int q0 = imax(lam.c0, y.r0), q1 = imin(lam.c0 + lam.n, y.r0 + y.m);
+  const int nq = q1 - q0, nr = rB - rA;
+  const int kl = lam.fmt ? rank_of(A, xi, l) : 0;
+  if (nq <= 0 || nq > KC || nr <= 0 || (lam.fmt ? kl > KC : nr > KC)) return false;
+  const int tid = threadIdx.x;
+  const int m = tc.m, n = tc.n;
+  const double alpha = P.alpha;
+  const LeafRef<T> lr = leaf_ref(A, xi, l, lam);
+  const T* uy = yr.U + (q0 - y.r0) + (int64_t)j0 * yr.ldu;
+  for (int idx = tid; idx < n * take; idx += TPB) {
+    const int c = idx / take, jj = idx - c * take;
+    const int gc = tc.c0 + c;
+    const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)yr.V[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
+    Vs[(int64_t)c * KC + K + jj] = (T)v;
+  }
+  for (int idx = tid; idx < m * take; idx += TPB) {
+    const int i = idx / take, jj = idx - i * take;
+    const int gi = tc.r0 + i;
+    if (gi < rA || gi >= rB) Us[(int64_t)i * KC + K + jj] = (T)0;
+  }
+  for (int idx = tid; idx < nq * take; idx += TPB) {
+    const int q = idx % nq, jj = idx / nq;
+    L.S2[q * KC + jj] = (double)uy[q + (int64_t)jj * yr.ldu];
+  }
+  if (lam.fmt) {
+    for (int idx = tid; idx < nq * kl; idx += TPB) {
+      const int q = idx % nq, a = idx / nq;
+      L.S1[q * KC + a] = (double)lr.V[(q0 - lam.c0) + q + (int64_t)a * lr.ldv];
+    }
+  } else {
+    for (int idx = tid; idx < nq * nr; idx += TPB) {
+      const int r = idx % nr, q = idx / nr;
+      L.S1[q * KC + r] = (double)lr.U[(rA - lam.r0) + r + (int64_t)(q0 - lam.c0 + q) * lr.ldu];
+    }
+  }
+  __syncthreads();
+  if (lam.fmt) {
+    for (int idx = tid; idx < kl * take; idx += TPB) {
+      const int a = idx / take, jj = idx - a * take;
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + a] * L.S2[q * KC + jj];
+      L.S0[a * KC + jj] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nr * take; idx += TPB) {
+      const int r = idx / take, jj = idx - r * take;
+      double s = 0.0;
+      for (int a = 0; a < kl; ++a) s += (double)lr.U[(rA - lam.r0) + r + (int64_t)a * lr.ldu] * L.S0[a * KC + jj];
+      Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
+    }
+    FLOP(L, 2.0 * kl * take * (nq + nr));
+  } else {
+    for (int idx = tid; idx < nr * take; idx += TPB) {
+      const int r = idx / take, jj = idx - r * take;
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + r] * L.S2[q * KC + jj];
+      Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
+    }
+    FLOP(L, 2.0 * nq * nr * take);
+  }
+  return true;
+}
+
 // Write columns [j0, j0+take) of a piece into scratch columns [K, K+take)
 // of Us (target rows) and Vs (target columns), row-major ld KC.  The alpha
 // of the piece is folded into Us.  LDS buffers S0 (products), S1, S2
@@ -662,6 +810,11 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const LeafRef<T> xr = leaf_ref(A, xi, P.xleaf, x);
     const T* Ux = xr.U;
     const T* Vx = xr.V;
+    if (lrx_single(A, P, tc, x, xr, yi, j0, take, Us, Vs, K, L)) {
+      __syncthreads();
+      PROF_ADD(PS_LRX, clock64() - tpc);
+      return;
+    }
     for (int idx = tid; idx < m * take; idx += TPB) {
       const int i = idx / take, jj = idx - i * take;
       const int gi = tc.r0 + i;
@@ -714,6 +867,11 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const LeafRef<T> yr = leaf_ref(A, yi, P.yleaf, y);
     const T* Uy = yr.U;
     const T* Vy = yr.V;
+    if (lry_single(A, P, tc, y, yr, xi, j0, take, Us, Vs, K, L)) {
+      __syncthreads();
+      PROF_ADD(PS_LRY, clock64() - tpc);
+      return;
+    }
     for (int idx = tid; idx < n * take; idx += TPB) {
       const int c = idx / take, jj = idx - c * take;
       const int gc = tc.c0 + c;
