@@ -78,6 +78,17 @@ __device__ __forceinline__ LeafRef<T> leaf_ref(const AccumArgs<T>& A, int inst, 
   return r;
 }
 
+// Arithmetic type of the staged piece products: FP32 for FP32 factors
+// (products accumulated in FP32), FP64 otherwise.
+template <typename T>
+struct CompT {
+  using type = double;
+};
+template <>
+struct CompT<float> {
+  using type = float;
+};
+
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
@@ -578,22 +589,24 @@ __device__ int piece_width(const AccumArgs<T>& A, int b, const Piece& P) {
 // operands contiguous along q), staged through LDS in chunks of KC along q.
 // Out is LDS with leading dimension KC; mo, no <= KC.
 template <typename T>
-__device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no, double* Out,
-                           double* bP, double* bR) {
+__device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no,
+                           typename CompT<T>::type* Out, typename CompT<T>::type* bP,
+                           typename CompT<T>::type* bR) {
+  using CT = typename CompT<T>::type;
   const int tid = threadIdx.x;
   constexpr int PER = (KC * KC + TPB - 1) / TPB;
-  double acc[PER];
+  CT acc[PER];
 #pragma unroll
-  for (int e = 0; e < PER; ++e) acc[e] = 0.0;
+  for (int e = 0; e < PER; ++e) acc[e] = 0;
   for (int q0 = 0; q0 < nq; q0 += KC) {
     const int nqq = imin(KC, nq - q0);
     for (int idx = tid; idx < nqq * mo; idx += TPB) {
       const int q = idx % nqq, i = idx / nqq;
-      bP[q * KC + i] = (double)P[q0 + q + (int64_t)i * ldp];
+      bP[q * KC + i] = (CT)P[q0 + q + (int64_t)i * ldp];
     }
     for (int idx = tid; idx < nqq * no; idx += TPB) {
       const int q = idx % nqq, j = idx / nqq;
-      bR[q * KC + j] = (double)R[q0 + q + (int64_t)j * ldr];
+      bR[q * KC + j] = (CT)R[q0 + q + (int64_t)j * ldr];
     }
     __syncthreads();
 #pragma unroll
@@ -601,7 +614,7 @@ __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int
       const int idx = tid + e * TPB;
       if (idx < mo * no) {
         const int i = idx / no, j = idx - i * no;
-        double s = 0.0;
+        CT s = 0;
         for (int q = 0; q < nqq; ++q) s += bP[q * KC + i] * bR[q * KC + j];
         acc[e] += s;
       }
@@ -623,19 +636,20 @@ __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int
 // a < na (<= KC), j < no (<= KC); M contiguous along i, Z in LDS.  `bM` is
 // an LDS staging buffer of KC x KC doubles.
 template <typename T>
-__device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const double* Z, int no, T* dst, int64_t drs,
-                       int64_t dcs, double alpha, double* bM) {
+__device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const typename CompT<T>::type* Z, int no, T* dst,
+                       int64_t drs, int64_t dcs, double alpha, typename CompT<T>::type* bM) {
+  using CT = typename CompT<T>::type;
   const int tid = threadIdx.x;
   for (int i0 = 0; i0 < mi; i0 += KC) {
     const int ni = imin(KC, mi - i0);
     for (int idx = tid; idx < ni * na; idx += TPB) {
       const int ii = idx % ni, a = idx / ni;
-      bM[a * KC + ii] = (double)M[(i0 + ii) + (int64_t)a * ldm];
+      bM[a * KC + ii] = (CT)M[(i0 + ii) + (int64_t)a * ldm];
     }
     __syncthreads();
     for (int idx = tid; idx < ni * no; idx += TPB) {
       const int j = idx % no, ii = idx / no;
-      double s = 0.0;
+      CT s = 0;
       for (int a = 0; a < na; ++a) s += bM[a * KC + ii] * Z[a * KC + j];
       T* d = dst + (int64_t)(i0 + ii) * drs + (int64_t)j * dcs;
       *d = (T)((double)*d + alpha * s);
@@ -654,6 +668,10 @@ __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const double* Z,
 template <typename T>
 __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& x,
                            const LeafRef<T>& xr, int yi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+  using CT = typename CompT<T>::type;
+  CT* S0c = reinterpret_cast<CT*>(L.S0);
+  CT* S1c = reinterpret_cast<CT*>(L.S1);
+  CT* S2c = reinterpret_cast<CT*>(L.S2);
   if (P.l1 - P.l0 != 1) return false;
   const int l = A.lists[P.l0];
   const DLeaf lam = A.leaves[l];
@@ -671,7 +689,7 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
     const int i = idx / take, jj = idx - i * take;
     const int gi = tc.r0 + i;
     const double v =
-        (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)xr.U[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
+        (gi >= P.wr0 && gi < P.wr1) ? alpha * (CT)xr.U[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
     Us[(int64_t)i * KC + K + jj] = (T)v;
   }
   for (int idx = tid; idx < n * take; idx += TPB) {
@@ -681,40 +699,40 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
   }
   for (int idx = tid; idx < nq * take; idx += TPB) {
     const int q = idx % nq, jj = idx / nq;
-    L.S2[q * KC + jj] = (double)vx[q + (int64_t)jj * xr.ldv];
+    S2c[q * KC + jj] = (CT)vx[q + (int64_t)jj * xr.ldv];
   }
   if (lam.fmt) {
     for (int idx = tid; idx < nq * kl; idx += TPB) {
       const int q = idx % nq, a = idx / nq;
-      L.S1[q * KC + a] = (double)lr.U[(q0 - lam.r0) + q + (int64_t)a * lr.ldu];
+      S1c[q * KC + a] = (CT)lr.U[(q0 - lam.r0) + q + (int64_t)a * lr.ldu];
     }
   } else {
     for (int idx = tid; idx < nq * nc; idx += TPB) {
       const int q = idx % nq, cc = idx / nq;
-      L.S1[q * KC + cc] = (double)lr.U[(q0 - lam.r0) + q + (int64_t)(cA - lam.c0 + cc) * lr.ldu];
+      S1c[q * KC + cc] = (CT)lr.U[(q0 - lam.r0) + q + (int64_t)(cA - lam.c0 + cc) * lr.ldu];
     }
   }
   __syncthreads();
   if (lam.fmt) {
     for (int idx = tid; idx < kl * take; idx += TPB) {
       const int a = idx / take, jj = idx - a * take;
-      double s = 0.0;
-      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + a] * L.S2[q * KC + jj];
-      L.S0[a * KC + jj] = s;
+      CT s = 0;
+      for (int q = 0; q < nq; ++q) s += S1c[q * KC + a] * S2c[q * KC + jj];
+      S0c[a * KC + jj] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < nc * take; idx += TPB) {
       const int cc = idx / take, jj = idx - cc * take;
-      double s = 0.0;
-      for (int a = 0; a < kl; ++a) s += (double)lr.V[(cA - lam.c0 + cc) + (int64_t)a * lr.ldv] * L.S0[a * KC + jj];
+      CT s = 0;
+      for (int a = 0; a < kl; ++a) s += (CT)lr.V[(cA - lam.c0 + cc) + (int64_t)a * lr.ldv] * S0c[a * KC + jj];
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
     FLOP(L, 2.0 * kl * take * (nq + nc));
   } else {
     for (int idx = tid; idx < nc * take; idx += TPB) {
       const int cc = idx / take, jj = idx - cc * take;
-      double s = 0.0;
-      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + cc] * L.S2[q * KC + jj];
+      CT s = 0;
+      for (int q = 0; q < nq; ++q) s += S1c[q * KC + cc] * S2c[q * KC + jj];
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
     FLOP(L, 2.0 * nq * nc * take);
@@ -725,6 +743,10 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
 template <typename T>
 __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& y,
                            const LeafRef<T>& yr, int xi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+  using CT = typename CompT<T>::type;
+  CT* S0c = reinterpret_cast<CT*>(L.S0);
+  CT* S1c = reinterpret_cast<CT*>(L.S1);
+  CT* S2c = reinterpret_cast<CT*>(L.S2);
   if (P.l1 - P.l0 != 1) return false;
   const int l = A.lists[P.l0];
   const DLeaf lam = A.leaves[l];
@@ -741,7 +763,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
   for (int idx = tid; idx < n * take; idx += TPB) {
     const int c = idx / take, jj = idx - c * take;
     const int gc = tc.c0 + c;
-    const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)yr.V[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
+    const double v = (gc >= P.wc0 && gc < P.wc1) ? (CT)yr.V[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
     Vs[(int64_t)c * KC + K + jj] = (T)v;
   }
   for (int idx = tid; idx < m * take; idx += TPB) {
@@ -751,40 +773,40 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
   }
   for (int idx = tid; idx < nq * take; idx += TPB) {
     const int q = idx % nq, jj = idx / nq;
-    L.S2[q * KC + jj] = (double)uy[q + (int64_t)jj * yr.ldu];
+    S2c[q * KC + jj] = (CT)uy[q + (int64_t)jj * yr.ldu];
   }
   if (lam.fmt) {
     for (int idx = tid; idx < nq * kl; idx += TPB) {
       const int q = idx % nq, a = idx / nq;
-      L.S1[q * KC + a] = (double)lr.V[(q0 - lam.c0) + q + (int64_t)a * lr.ldv];
+      S1c[q * KC + a] = (CT)lr.V[(q0 - lam.c0) + q + (int64_t)a * lr.ldv];
     }
   } else {
     for (int idx = tid; idx < nq * nr; idx += TPB) {
       const int r = idx % nr, q = idx / nr;
-      L.S1[q * KC + r] = (double)lr.U[(rA - lam.r0) + r + (int64_t)(q0 - lam.c0 + q) * lr.ldu];
+      S1c[q * KC + r] = (CT)lr.U[(rA - lam.r0) + r + (int64_t)(q0 - lam.c0 + q) * lr.ldu];
     }
   }
   __syncthreads();
   if (lam.fmt) {
     for (int idx = tid; idx < kl * take; idx += TPB) {
       const int a = idx / take, jj = idx - a * take;
-      double s = 0.0;
-      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + a] * L.S2[q * KC + jj];
-      L.S0[a * KC + jj] = s;
+      CT s = 0;
+      for (int q = 0; q < nq; ++q) s += S1c[q * KC + a] * S2c[q * KC + jj];
+      S0c[a * KC + jj] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < nr * take; idx += TPB) {
       const int r = idx / take, jj = idx - r * take;
-      double s = 0.0;
-      for (int a = 0; a < kl; ++a) s += (double)lr.U[(rA - lam.r0) + r + (int64_t)a * lr.ldu] * L.S0[a * KC + jj];
+      CT s = 0;
+      for (int a = 0; a < kl; ++a) s += (CT)lr.U[(rA - lam.r0) + r + (int64_t)a * lr.ldu] * S0c[a * KC + jj];
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
     FLOP(L, 2.0 * kl * take * (nq + nr));
   } else {
     for (int idx = tid; idx < nr * take; idx += TPB) {
       const int r = idx / take, jj = idx - r * take;
-      double s = 0.0;
-      for (int q = 0; q < nq; ++q) s += L.S1[q * KC + r] * L.S2[q * KC + jj];
+      CT s = 0;
+      for (int q = 0; q < nq; ++q) s += S1c[q * KC + r] * S2c[q * KC + jj];
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
     FLOP(L, 2.0 * nq * nr * take);
@@ -799,6 +821,10 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
 template <typename T>
 __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0, int take,
                               T* Us, T* Vs, int K, Lds& L) {
+  using CT = typename CompT<T>::type;
+  CT* S0c = reinterpret_cast<CT*>(L.S0);
+  CT* S1c = reinterpret_cast<CT*>(L.S1);
+  CT* S2c = reinterpret_cast<CT*>(L.S2);
   const int tid = threadIdx.x;
   const int m = tc.m, n = tc.n;
   const double alpha = P.alpha;
@@ -819,7 +845,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int i = idx / take, jj = idx - i * take;
       const int gi = tc.r0 + i;
       const double v =
-          (gi >= P.wr0 && gi < P.wr1) ? alpha * (double)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
+          (gi >= P.wr0 && gi < P.wr1) ? alpha * (CT)Ux[(gi - x.r0) + (int64_t)(j0 + jj) * xr.ldu] : 0.0;
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
@@ -840,13 +866,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       if (lam.fmt == 0) {
         for (int c0 = cA; c0 < cB; c0 += KC) {
           const int nc = imin(KC, cB - c0);
-          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, L.S0, L.S1,
-                     L.S2);
+          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, S0c, S1c,
+                     S2c);
           FLOP(L, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
             T* d = &Vs[(int64_t)(c0 + cc - tc.c0) * KC + K + jj];
-            *d = (T)((double)*d + L.S0[cc * KC + jj]);
+            *d = (T)((CT)*d + S0c[cc * KC + jj]);
           }
           __syncthreads();
         }
@@ -855,9 +881,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, L.S0, L.S1, L.S2);
-        nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, L.S0, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
-               L.S1);
+        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c);
+        nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, S0c, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
+               S1c);
         FLOP(L, 2.0 * kl * take * (nq + (cB - cA)));
       }
     }
@@ -875,7 +901,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     for (int idx = tid; idx < n * take; idx += TPB) {
       const int c = idx / take, jj = idx - c * take;
       const int gc = tc.c0 + c;
-      const double v = (gc >= P.wc0 && gc < P.wc1) ? (double)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
+      const double v = (gc >= P.wc0 && gc < P.wc1) ? (CT)Vy[(gc - y.c0) + (int64_t)(j0 + jj) * yr.ldv] : 0.0;
       Vs[(int64_t)c * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < m * take; idx += TPB) {
@@ -898,11 +924,11 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           const int nqc = imin(KC, nq - qc);
           for (int idx = tid; idx < nqc * take; idx += TPB) {
             const int q = idx % nqc, jj = idx / nqc;
-            L.S0[q * KC + jj] = (double)uy[qc + q + (int64_t)jj * yr.ldu];
+            S0c[q * KC + jj] = (CT)uy[qc + q + (int64_t)jj * yr.ldu];
           }
           __syncthreads();
-          nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, L.S0, take,
-                 Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, L.S1);
+          nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, S0c, take,
+                 Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, S1c);
           FLOP(L, 2.0 * (rB - rA) * nqc * take);
         }
       } else {
@@ -910,9 +936,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, L.S0, L.S1, L.S2);
-        nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, L.S0, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
-               L.S1);
+        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c);
+        nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, S0c, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
+               S1c);
         FLOP(L, 2.0 * kl * take * (nq + (rB - rA)));
       }
     }
@@ -937,11 +963,11 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       const int nqc = imin(KC, M1 - qc);
       for (int idx = tid; idx < nqc * take; idx += TPB) {
         const int q = idx % nqc, jj = idx / nqc;
-        L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(P.wc0 + j0 + jj - y.c0) * yr.ldu];
+        S0c[q * KC + jj] = (CT)yp[(qc + q - y.r0) + (int64_t)(P.wc0 + j0 + jj - y.c0) * yr.ldu];
       }
       __syncthreads();
-      nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, L.S0, take,
-             Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, L.S1);
+      nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, take,
+             Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, S1c);
       FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * take);
     }
   } else {  // PK_COPY of a low-rank leaf
@@ -954,13 +980,13 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
     for (int idx = tid; idx < m * take; idx += TPB) {
       const int i = idx / take, jj = idx - i * take;
-      double v = alpha * (double)Usrc[i + (int64_t)(j0 + jj) * sr.ldu];
+      double v = alpha * (CT)Usrc[i + (int64_t)(j0 + jj) * sr.ldu];
       if (rho) v *= rho[tc.r0 + i];
       Us[(int64_t)i * KC + K + jj] = (T)v;
     }
     for (int idx = tid; idx < n * take; idx += TPB) {
       const int c = idx / take, jj = idx - c * take;
-      double v = (double)Vsrc[c + (int64_t)(j0 + jj) * sr.ldv];
+      double v = (CT)Vsrc[c + (int64_t)(j0 + jj) * sr.ldv];
       if (gam) v *= gam[tc.c0 + c];
       Vs[(int64_t)c * KC + K + jj] = (T)v;
     }
@@ -973,26 +999,30 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
 // Dense target: C += Us Vs^T for `take` columns (C column-major m x n).
 template <typename T>
 __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, Lds& L) {
+  using CT = typename CompT<T>::type;
+  CT* S0c = reinterpret_cast<CT*>(L.S0);
+  CT* S1c = reinterpret_cast<CT*>(L.S1);
+  CT* S2c = reinterpret_cast<CT*>(L.S2);
   const int tid = threadIdx.x;
   for (int c0 = 0; c0 < tc.n; c0 += KC) {
     const int nc = imin(KC, tc.n - c0);
     for (int idx = tid; idx < nc * take; idx += TPB) {
       const int jj = idx % take, cc = idx / take;
-      L.S0[jj * KC + cc] = (double)Vs[(int64_t)(c0 + cc) * KC + jj];
+      S0c[jj * KC + cc] = (CT)Vs[(int64_t)(c0 + cc) * KC + jj];
     }
     for (int i0 = 0; i0 < tc.m; i0 += KC) {
       const int ni = imin(KC, tc.m - i0);
       for (int idx = tid; idx < ni * take; idx += TPB) {
         const int jj = idx % take, ii = idx / take;
-        L.S1[jj * KC + ii] = (double)Us[(int64_t)(i0 + ii) * KC + jj];
+        S1c[jj * KC + ii] = (CT)Us[(int64_t)(i0 + ii) * KC + jj];
       }
       __syncthreads();
       for (int idx = tid; idx < ni * nc; idx += TPB) {
         const int ii = idx % ni, cc = idx / ni;
-        double s = 0.0;
-        for (int jj = 0; jj < take; ++jj) s += L.S1[jj * KC + ii] * L.S0[jj * KC + cc];
+        CT s = 0;
+        for (int jj = 0; jj < take; ++jj) s += S1c[jj * KC + ii] * S0c[jj * KC + cc];
         T* d = &C[(i0 + ii) + (int64_t)(c0 + cc) * tc.m];
-        *d = (T)((double)*d + s);
+        *d = (T)((CT)*d + s);
       }
       __syncthreads();
     }
@@ -1006,6 +1036,10 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
 template <typename T>
 __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
                              Lds& L) {
+  using CT = typename CompT<T>::type;
+  CT* S0c = reinterpret_cast<CT*>(L.S0);
+  CT* S1c = reinterpret_cast<CT*>(L.S1);
+  CT* S2c = reinterpret_cast<CT*>(L.S2);
   const int tid = threadIdx.x;
   unsigned long long* prof = A.prof;
   for (int p = tg.p0; p < tg.p1; ++p) {
@@ -1025,11 +1059,11 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
           const int nqc = imin(KC, M1 - qc);
           for (int idx = tid; idx < nqc * nc; idx += TPB) {
             const int q = idx % nqc, jj = idx / nqc;
-            L.S0[q * KC + jj] = (double)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * yr.ldu];
+            S0c[q * KC + jj] = (CT)yp[(qc + q - y.r0) + (int64_t)(cc0 + jj - y.c0) * yr.ldu];
           }
           __syncthreads();
-          nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, L.S0, nc,
-                 C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, L.S1);
+          nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, nc,
+                 C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, S1c);
           FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
         }
       }
@@ -1043,10 +1077,10 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       const double* gam = P.cv >= 0 ? A.vec_ptr[b * A.nvroles + P.cv] : nullptr;
       for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
         int i = idx % tc.m, c = idx / tc.m;
-        double v = P.alpha * (double)src[i + (int64_t)c * sr.ldu];
+        double v = P.alpha * (CT)src[i + (int64_t)c * sr.ldu];
         if (rho) v *= rho[tc.r0 + i];
         if (gam) v *= gam[tc.c0 + c];
-        C[idx] = (T)((double)C[idx] + v);
+        C[idx] = (T)((CT)C[idx] + v);
       }
       __syncthreads();
     } else {
