@@ -228,6 +228,30 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     if (d_soff) dfree(d_soff);
     d_lr_leaves = upload(lrl);
     d_soff = upload(soff);
+    // coefficient kernel order: low-rank leaves by the lane-group class of
+    // the factor length it reduces over (n for V^T x, m for U^T x)
+    auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6]) {
+      auto cl = [](int len) { return len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : len <= 128 ? 3 : 4; };
+      std::vector<int32_t> v(lrl);
+      std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+        return cl(use_m ? G.lf[a].m : G.lf[a].n) < cl(use_m ? G.lf[b].m : G.lf[b].n);
+      });
+      int cnt[5] = {0, 0, 0, 0, 0};
+      for (int l : v) cnt[cl(use_m ? G.lf[l].m : G.lf[l].n)]++;
+      cls[0] = 0;
+      cw[0][0] = cw[1][0] = 0;
+      for (int c = 0; c < 5; ++c) {
+        cls[c + 1] = cls[c] + cnt[c];
+        for (int ri = 0; ri < 2; ++ri) {
+          const int per_wave = (ri ? 4 : 1) * (64 >> (c + 2));  // rounds of 64 / G leaves
+          cw[ri][c + 1] = cw[ri][c] + (cnt[c] + per_wave - 1) / per_wave;
+        }
+      }
+      if (dst) dfree(dst);
+      dst = upload(v);
+    };
+    by_class(false, d_lr_n, cls_n, cw_n);
+    by_class(true, d_lr_t, cls_t, cw_t);
     // level-0 scatter map: in-plane couplings -> dense leaf entries
     std::vector<int64_t> map(5 * (size_t)B, -1);
     std::vector<int> pos(B);
@@ -595,15 +619,6 @@ void Handle::build_apply_jobs() {
   coef = dnew<double>((size_t)std::max(max_jobs, 1) * 2 * sstride);
 }
 
-// Low-rank leaves per wavefront of the coefficient kernel: enough
-// wavefronts to fill the chip (~12k), at most 64 leaves each.
-static int coef_chunk(int nterms, int nlr) {
-  const int64_t work = (int64_t)nterms * nlr;
-  int c = 1;
-  while (c < 64 && work / (2 * c) >= 12288) c *= 2;
-  return c;
-}
-
 void Handle::apply(const std::vector<const double*>& r, const std::vector<double*>& out, bool transpose, int prob,
                    hipStream_t s) {
   sync_tables();
@@ -628,7 +643,17 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.terms = pj.terms;
       a.nterms = pj.nterms;
       a.trans = pj.trans;
-      a.chunk = coef_chunk(pj.nterms, G.nlr);
+      a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
+      {
+        // four leaves per lane group when the phase fills the chip anyway
+        const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
+        const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
+        a.rounds = ri ? 4 : 1;
+        for (int c = 0; c < 6; ++c) {
+          a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
+          a.cw[c] = cw[ri][c];
+        }
+      }
       a.inst_base = (float* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
       a.inst_off = d_inst_off;
@@ -652,7 +677,17 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
       a.terms = pj.terms;
       a.nterms = pj.nterms;
       a.trans = pj.trans;
-      a.chunk = coef_chunk(pj.nterms, G.nlr);
+      a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
+      {
+        // four leaves per lane group when the phase fills the chip anyway
+        const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
+        const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
+        a.rounds = ri ? 4 : 1;
+        for (int c = 0; c < 6; ++c) {
+          a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
+          a.cw[c] = cw[ri][c];
+        }
+      }
       a.inst_base = (double* const*)d_inst_base;
       a.inst_rank = d_inst_rank;
       a.inst_off = d_inst_off;

@@ -114,7 +114,13 @@ struct MvArgs {
   const int32_t* terms;       // non-empty H-matrix terms of the phase: 2 * job + term
   int32_t nterms;
   int32_t trans;              // 1: every term of the phase is transposed
-  int32_t chunk;              // low-rank leaves per wavefront in the coefficient kernel (<= 64)
+  int32_t rounds;             // leaves per lane group and wavefront in the coefficient kernel (1 or 4)
+  // low-rank leaves ordered by the lane-group class of their column length
+  // (4, 8, 16, 32, 64 lanes); cls[c] = first leaf of class c in lr_sorted,
+  // cw[c] = first wavefront of class c within one job term (for `rounds`)
+  const int32_t* lr_sorted;
+  int32_t cls[6];
+  int32_t cw[6];
   T* const* inst_base;
   int32_t* const* inst_rank;
   const int64_t* const* inst_off;  // packed per-leaf offsets (every factor is packed)

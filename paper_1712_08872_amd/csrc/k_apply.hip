@@ -60,60 +60,72 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
-// One wavefront per (job term, chunk of A.chunk consecutive low-rank leaves).
+// s = V^T x (or U^T x) for every low-rank leaf of a job term.  The leaves
+// are ordered by the class of the length len they reduce over; a leaf of
+// class c gets a group of G = 4 << c lanes (a 16-byte quad of each column
+// per lane), so a wavefront works on 64 / G leaves at once (1 or 4 rounds),
+// with the column loads of a leaf in flight together; each column is
+// reduced within its lane group.
 template <typename T>
 __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
   const int lane = threadIdx.x & 63;
-  const int nch = (A.nlr + A.chunk - 1) / A.chunk;
-  const int64_t nitems = (int64_t)A.nterms * nch;
+  const int W = A.cw[5];
+  const int64_t nitems = (int64_t)A.nterms * W;
   for (int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); item < nitems; item += (int64_t)gridDim.x * 4) {
-    const int ti = (int)(item / nch);
-    const int li0 = (int)(item - (int64_t)ti * nch) * A.chunk;
-    const int cnt = imin_(A.chunk, A.nlr - li0);
+    const int ti = (int)(item / W);
+    const int wv = (int)(item - (int64_t)ti * W);
+    int c = 0;
+    while (c < 4 && wv >= A.cw[c + 1]) ++c;
+    const int G = 4 << c, groups = 64 / G;
+    const int gi = lane / G, q = lane & (G - 1);
+    const int lb = A.cls[c] + (wv - A.cw[c]) * A.rounds * groups, cend = A.cls[c + 1];
     const int jt = A.terms[ti];
     const MvTerm& tm = A.jobs[jt >> 1].t[jt & 1];
     const T* base = A.inst_base[tm.inst];
     double* coef = A.coef + (int64_t)jt * A.sstride;
-    // lane-parallel descriptors
-    int dlen = 0, dld = 0, dk = 0, dx = 0;
-    int64_t doff = 0, dso = 0;
-    if (lane < cnt) {
-      const int l = A.lr_leaves[li0 + lane];
+    for (int r = 0; r < A.rounds; ++r) {
+      const int li = lb + r * groups + gi;
+      if (li >= cend) continue;  // a whole lane group at a time
+      const int l = A.lr_sorted[li];
       const DLeaf L = A.leaves[l];
-      dk = A.inst_rank[tm.inst][l];
+      const int k = A.inst_rank[tm.inst][l];
       const int ldu = pad4(L.m), ldv = pad4(L.n);
-      // transposed: s = U^T x[rows]; otherwise s = V^T x[cols]
-      doff = A.inst_off[tm.inst][l] + (A.trans ? 0 : (int64_t)ldu * dk);
-      dlen = A.trans ? L.m : L.n;
-      dld = A.trans ? ldu : ldv;
-      dx = A.trans ? L.r0 : L.c0;
-      dso = A.soff[l];
-    }
-    for (int i = 0; i < cnt; ++i) {
-      const int k = bcast(dk, i);
-      if (k == 0) continue;
-      const int len = bcast(dlen, i), ld = bcast(dld, i);
-      const T* F = base + bcast64(doff, i);
-      const double* x = tm.x + bcast(dx, i);
-      double* out = coef + bcast64(dso, i);
-      const int g = lanes_per_col(len), cpp = 64 / g;
-      const int q = lane & (g - 1), co = lane / g;
-      for (int a0 = 0; a0 < k; a0 += cpp) {
-        const int a = a0 + co;
-        double s = 0.0;
-        if (a < k) {
-          const T* f = F + (int64_t)a * ld;
+      const T* F = base + A.inst_off[tm.inst][l] + (A.trans ? 0 : (int64_t)ldu * k);
+      const int len = A.trans ? L.m : L.n, ld = A.trans ? ldu : ldv;
+      const double* x = tm.x + (A.trans ? L.r0 : L.c0);
+      double* out = coef + A.soff[l];
+      if (len <= 4 * G) {  // one quad per lane and column: x once, the columns' loads together
+        const int r0 = 4 * q;
+        double xv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
+        const bool act = r0 < len;
 #pragma unroll 4
-          for (int r = 4 * q; r < len; r += 4 * g) {
+        for (int a = 0; a < k; ++a) {
+          double s = 0.0;
+          if (act) {
             double v[4];
-            load4(f + r, v);
+            load4(F + (int64_t)a * ld + r0, v);
+            s = v[0] * xv[0] + v[1] * xv[1] + v[2] * xv[2] + v[3] * xv[3];
+          }
+          for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+          if (q == 0) out[a] = s;
+        }
+      } else {
+        for (int a = 0; a < k; ++a) {
+          const T* f = F + (int64_t)a * ld;
+          double s = 0.0;
+#pragma unroll 4
+          for (int r0 = 4 * q; r0 < len; r0 += 4 * G) {
+            double v[4];
+            load4(f + r0, v);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-              if (r + e < len) s += v[e] * x[r + e];
+              if (r0 + e < len) s += v[e] * x[r0 + e];
           }
+          for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
+          if (q == 0) out[a] = s;
         }
-        for (int o = g >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (q == 0 && a < k) out[a] = s;
       }
     }
   }
@@ -396,7 +408,7 @@ template void launch_pack<float>(const float*, const int32_t*, const DLeaf*, int
 
 template <typename T>
 void launch_mv(const MvArgs<T>& a, hipStream_t s) {
-  const int64_t n1 = ((int64_t)a.nterms * ((a.nlr + a.chunk - 1) / a.chunk) + 3) / 4;
+  const int64_t n1 = ((int64_t)a.nterms * a.cw[5] + 3) / 4;
   const int g1 = (int)(n1 < 16384 ? n1 : 16384);
   if (g1 > 0) hipLaunchKernelGGL(mv_coef_kernel<T>, dim3(g1), dim3(256), 0, s, a);
   const int64_t n2 = (int64_t)a.njobs * a.nseg;

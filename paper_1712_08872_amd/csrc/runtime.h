@@ -143,6 +143,9 @@ struct Handle {
   int32_t *d_seg_lo = nullptr, *d_rows_ptr = nullptr, *d_rows_idx = nullptr, *d_cols_ptr = nullptr,
           *d_cols_idx = nullptr, *d_lr_leaves = nullptr;
   int64_t* d_soff = nullptr;
+  int32_t *d_lr_n = nullptr, *d_lr_t = nullptr;  // low-rank leaves by lane class of n (of m)
+  int32_t cls_n[6] = {0}, cls_t[6] = {0};
+  int32_t cw_n[2][6] = {{0}}, cw_t[2][6] = {{0}};  // wavefront offsets for 1 and 4 rounds
   int64_t sstride = 0;
   // instances
   std::vector<Instance> inst;
