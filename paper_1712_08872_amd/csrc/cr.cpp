@@ -230,28 +230,35 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     d_soff = upload(soff);
     // coefficient kernel order: low-rank leaves by the lane-group class of
     // the factor length it reduces over (n for V^T x, m for U^T x)
-    auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6]) {
+    auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6], int32_t& w4) {
       auto cl = [](int len) { return len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : len <= 128 ? 3 : 4; };
       std::vector<int32_t> v(lrl);
       std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
         return cl(use_m ? G.lf[a].m : G.lf[a].n) < cl(use_m ? G.lf[b].m : G.lf[b].n);
       });
       int cnt[5] = {0, 0, 0, 0, 0};
-      for (int l : v) cnt[cl(use_m ? G.lf[l].m : G.lf[l].n)]++;
+      int cap4 = 1;
+      for (int l : v) {
+        const int c = cl(use_m ? G.lf[l].m : G.lf[l].n);
+        cnt[c]++;
+        if (c == 4) cap4 = std::max(cap4, G.lf[l].cap);
+      }
+      // the longest leaves: one wavefront per 4 columns of a leaf
+      w4 = (cap4 + 3) / 4;
       cls[0] = 0;
       cw[0][0] = cw[1][0] = 0;
       for (int c = 0; c < 5; ++c) {
         cls[c + 1] = cls[c] + cnt[c];
         for (int ri = 0; ri < 2; ++ri) {
           const int per_wave = (ri ? 4 : 1) * (64 >> (c + 2));  // rounds of 64 / G leaves
-          cw[ri][c + 1] = cw[ri][c] + (cnt[c] + per_wave - 1) / per_wave;
+          cw[ri][c + 1] = cw[ri][c] + (c < 4 ? (cnt[c] + per_wave - 1) / per_wave : cnt[c] * w4);
         }
       }
       if (dst) dfree(dst);
       dst = upload(v);
     };
-    by_class(false, d_lr_n, cls_n, cw_n);
-    by_class(true, d_lr_t, cls_t, cw_t);
+    by_class(false, d_lr_n, cls_n, cw_n, w4_n);
+    by_class(true, d_lr_t, cls_t, cw_t, w4_t);
     // level-0 scatter map: in-plane couplings -> dense leaf entries
     std::vector<int64_t> map(5 * (size_t)B, -1);
     std::vector<int> pos(B);
@@ -649,6 +656,7 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
         const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
         const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
         a.rounds = ri ? 4 : 1;
+        a.w4 = pj.trans ? w4_t : w4_n;
         for (int c = 0; c < 6; ++c) {
           a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
           a.cw[c] = cw[ri][c];
@@ -683,6 +691,7 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
         const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
         const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
         a.rounds = ri ? 4 : 1;
+        a.w4 = pj.trans ? w4_t : w4_n;
         for (int c = 0; c < 6; ++c) {
           a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
           a.cw[c] = cw[ri][c];

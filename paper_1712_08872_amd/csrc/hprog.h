@@ -115,6 +115,7 @@ struct MvArgs {
   int32_t nterms;
   int32_t trans;              // 1: every term of the phase is transposed
   int32_t rounds;             // leaves per lane group and wavefront in the coefficient kernel (1 or 4)
+  int32_t w4;                 // wavefronts per leaf of the longest class (4 columns each)
   // low-rank leaves ordered by the lane-group class of their column length
   // (4, 8, 16, 32, 64 lanes); cls[c] = first leaf of class c in lr_sorted,
   // cw[c] = first wavefront of class c within one job term (for `rounds`)

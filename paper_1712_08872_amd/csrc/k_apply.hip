@@ -78,11 +78,40 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
     while (c < 4 && wv >= A.cw[c + 1]) ++c;
     const int G = 4 << c, groups = 64 / G;
     const int gi = lane / G, q = lane & (G - 1);
-    const int lb = A.cls[c] + (wv - A.cw[c]) * A.rounds * groups, cend = A.cls[c + 1];
     const int jt = A.terms[ti];
     const MvTerm& tm = A.jobs[jt >> 1].t[jt & 1];
     const T* base = A.inst_base[tm.inst];
     double* coef = A.coef + (int64_t)jt * A.sstride;
+    if (c == 4) {  // longest leaves: this wavefront takes 4 columns of one leaf
+      const int rel = wv - A.cw[4];
+      const int l = A.lr_sorted[A.cls[4] + rel / A.w4];
+      const int a0 = 4 * (rel % A.w4);
+      const DLeaf L = A.leaves[l];
+      const int k = A.inst_rank[tm.inst][l];
+      if (a0 >= k) continue;
+      const int ldu = pad4(L.m), ldv = pad4(L.n);
+      const T* F = base + A.inst_off[tm.inst][l] + (A.trans ? 0 : (int64_t)ldu * k);
+      const int len = A.trans ? L.m : L.n, ld = A.trans ? ldu : ldv;
+      const double* x = tm.x + (A.trans ? L.r0 : L.c0);
+      double* out = coef + A.soff[l];
+      const int a1 = imin_(k, a0 + 4);
+      for (int a = a0; a < a1; ++a) {
+        const T* f = F + (int64_t)a * ld;
+        double s = 0.0;
+#pragma unroll 4
+        for (int r0 = 4 * lane; r0 < len; r0 += 256) {
+          double v[4];
+          load4(f + r0, v);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r0 + e < len) s += v[e] * x[r0 + e];
+        }
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) out[a] = s;
+      }
+      continue;
+    }
+    const int lb = A.cls[c] + (wv - A.cw[c]) * A.rounds * groups, cend = A.cls[c + 1];
     for (int r = 0; r < A.rounds; ++r) {
       const int li = lb + r * groups + gi;
       if (li >= cend) continue;  // a whole lane group at a time

@@ -146,6 +146,7 @@ struct Handle {
   int32_t *d_lr_n = nullptr, *d_lr_t = nullptr;  // low-rank leaves by lane class of n (of m)
   int32_t cls_n[6] = {0}, cls_t[6] = {0};
   int32_t cw_n[2][6] = {{0}}, cw_t[2][6] = {{0}};  // wavefront offsets for 1 and 4 rounds
+  int32_t w4_n = 1, w4_t = 1;                       // wavefronts per leaf of the longest class
   int64_t sstride = 0;
   // instances
   std::vector<Instance> inst;
