@@ -26,6 +26,7 @@ Also printed (same JSON line):
                    complexity; rank 0, N=1 only.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -38,6 +39,48 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 METRIC = "ACR setup+solve secs to 1e-8 resid, 127^3 Poisson; mixed vs FP64 GPU speedup"
+
+
+# HBM traffic of the accumulation kernel from rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE passes (profiles/accum_kernel_traffic.json), valid only for the
+# kernel source it was measured on.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "accum_kernel_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_08872_amd", "csrc", f) for f in ("k_harith.hip", "hprog.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per accumulation launch from the committed counter record, or
+    None when it is absent or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def copy_probe(mib):
+    """A plain device copy of known size, for calibrating FETCH_SIZE /
+    WRITE_SIZE (rocprofv3 --pmc ... -- python bench.py --copy-probe MIB)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3}), flush=True)
 
 
 def _inputs(n, seed_offset=0):
@@ -115,11 +158,16 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the plane-sharded multi-GPU "
               f"path is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     os.environ["ACR_KERNEL_TIMING"] = "1"
     import torch
     import paper_1712_08872_amd as acr
@@ -160,8 +208,10 @@ def main():
     per_launch_s = st["accum_seconds"] / launches
     per_launch_flops = st["accum_flops"] / launches
     tf = per_launch_flops / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
+    traffic = measured_traffic()
     roof = {"bound": "alu", "achieved": round(tf, 4), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 6), "traffic": None, "kernel": "accum_kernel",
+            "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 6),
+            "traffic": round(traffic) if traffic is not None else None, "kernel": "accum_kernel",
             "launches": st["accum_launches"], "mean_launch_ms": round(per_launch_s * 1e3, 4),
             "flops_per_launch": per_launch_flops}
     out = {"metric": METRIC, "value": round(t_mixed, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
