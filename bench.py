@@ -20,7 +20,8 @@ Also printed (same JSON line):
                    bound): algorithmic FP64 flops per launch / mean launch
                    duration (HIP events on its stream) vs 78.6 TFLOP/s
   apply_roofline-- the preconditioner application (HBM bound):
-                   algorithmic bytes per apply / apply time vs 8 TB/s
+                   algorithmic bytes per apply / apply time vs 8 TB/s, for
+                   the mixed handle (apply_roofline_fp64: the FP64 one)
   cpu_baseline  -- the CPU FP64 oracle on a bounded sample (same recipe at
                    23^3, ~20 s), projected to 127^3 by the N log^2 N setup
                    complexity; rank 0, N=1 only.
@@ -194,12 +195,15 @@ def main():
     st = mixed[-1]["stats"]
     aroof = apply_roofline(acr, torch, last, f)
     del last
+    aroof64 = None
     if not args.no_fp64:
         for k in range(args.steps):
             h, _, r = gpu_step(acr, torch, n, kap, f, acr.FP64, args.eps, args.rtol)
             fp64.append(r)
             print(f"[bench] fp64 step {k}: {r['seconds']:.2f} s (setup {r['setup_s']:.2f}, "
                   f"solve {r['solve_s']:.3f}, {r['iters']} iters)", file=sys.stderr, flush=True)
+            if k == args.steps - 1:
+                aroof64 = apply_roofline(acr, torch, h, f)
             del h
     t_mixed = sum(r["seconds"] for r in mixed) / len(mixed)
     t_fp64 = sum(r["seconds"] for r in fp64) / len(fp64) if fp64 else None
@@ -228,7 +232,7 @@ def main():
            "fp64_solve_s": round(fp64[-1]["solve_s"], 4) if fp64 else None,
            "fp64_iters": fp64[-1]["iters"] if fp64 else None,
            "max_rank": st["max_rank_all"], "factor_GB": round(st["bytes_factors"] / 1e9, 2),
-           "roofline": roof, "apply_roofline": aroof}
+           "roofline": roof, "apply_roofline": aroof, "apply_roofline_fp64": aroof64}
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(eps=args.eps)
     else:
