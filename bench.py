@@ -16,9 +16,12 @@ FP64 for the mixed-vs-FP64 speedup.  `value` is the mean mixed-precision
 seconds per step (lower is better).
 
 Also printed (same JSON line):
-  roofline      -- the dominant kernel (H-arithmetic accumulation, ALU
-                   bound): algorithmic FP64 flops per launch / mean launch
-                   duration (HIP events on its stream) vs 78.6 TFLOP/s
+  roofline      -- the dominant kernel of the H-arithmetic steps (ALU
+                   bound): algorithmic flops per launch / mean launch
+                   duration (HIP events on its stream), against 78.6
+                   TFLOP/s (truncating kernel, FP64 cores) or 157.3 TFLOP/s
+                   (accumulate-only kernel, FP32 products);
+                   roofline_second_kernel -- the other one
   apply_roofline-- the preconditioner application (HBM bound):
                    algorithmic bytes per apply / apply time vs 8 TB/s, for
                    the mixed handle (apply_roofline_fp64: the FP64 one)
@@ -39,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "ACR setup+solve secs to 1e-8 resid, 127^3 Poisson; mixed vs FP64 GPU speedup"
 
 
@@ -57,8 +61,8 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per accumulation launch from the committed counter record, or
+def measured_traffic(kernel):
+    """Bytes per launch of `kernel` from the committed counter record, or
     None when it is absent or was taken on a different kernel source."""
     try:
         with open(TRAFFIC_RECORD) as fh:
@@ -67,7 +71,21 @@ def measured_traffic():
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec.get("kernels", {}).get(kernel, {}).get("traffic_bytes_per_launch")
+
+
+def kernel_roofline(name, launches, seconds, flops, peak):
+    """Algorithmic flops per launch over the mean launch duration (HIP
+    events around every launch on its stream)."""
+    launches = max(launches, 1)
+    per_s = seconds / launches
+    per_f = flops / launches
+    tf = per_f / per_s / 1e12 if per_s > 0 else 0.0
+    traffic = measured_traffic(name)
+    return {"bound": "alu", "achieved": round(tf, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 6),
+            "traffic": round(traffic) if traffic is not None else None, "kernel": name, "launches": launches,
+            "mean_launch_ms": round(per_s * 1e3, 4), "flops_per_launch": per_f,
+            "total_seconds": round(seconds, 3)}
 
 
 def copy_probe(mib):
@@ -207,17 +225,14 @@ def main():
             del h
     t_mixed = sum(r["seconds"] for r in mixed) / len(mixed)
     t_fp64 = sum(r["seconds"] for r in fp64) / len(fp64) if fp64 else None
-    # dominant kernel: H-arithmetic accumulation (ALU bound)
-    launches = max(st["accum_launches"], 1)
-    per_launch_s = st["accum_seconds"] / launches
-    per_launch_flops = st["accum_flops"] / launches
-    tf = per_launch_flops / per_launch_s / 1e12 if per_launch_s > 0 else 0.0
-    traffic = measured_traffic()
-    roof = {"bound": "alu", "achieved": round(tf, 4), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 6),
-            "traffic": round(traffic) if traffic is not None else None, "kernel": "accum_kernel",
-            "launches": st["accum_launches"], "mean_launch_ms": round(per_launch_s * 1e3, 4),
-            "flops_per_launch": per_launch_flops}
+    # H-arithmetic kernels (ALU bound): the truncating kernel (FP64 Gram
+    # matrices and cores) and the accumulate-only kernel (FP32 products with
+    # FP32 factors); `roofline` is the one with the larger total time
+    kt = kernel_roofline("accum_kernel", st["accum_launches"], st["accum_seconds"], st["accum_flops"],
+                         FP64_VECTOR_PEAK_TFLOPS)
+    kd = kernel_roofline("accum_dense_kernel", st["dense_launches"], st["dense_seconds"], st["dense_flops"],
+                         FP32_VECTOR_PEAK_TFLOPS)
+    roof, roof2 = (kt, kd) if st["accum_seconds"] >= st["dense_seconds"] else (kd, kt)
     out = {"metric": METRIC, "value": round(t_mixed, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3, 1), "higher_is_better": False,
            "scaling": "strong", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
@@ -232,7 +247,8 @@ def main():
            "fp64_solve_s": round(fp64[-1]["solve_s"], 4) if fp64 else None,
            "fp64_iters": fp64[-1]["iters"] if fp64 else None,
            "max_rank": st["max_rank_all"], "factor_GB": round(st["bytes_factors"] / 1e9, 2),
-           "roofline": roof, "apply_roofline": aroof, "apply_roofline_fp64": aroof64}
+           "roofline": roof, "roofline_second_kernel": roof2, "apply_roofline": aroof,
+           "apply_roofline_fp64": aroof64}
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(eps=args.eps)
     else:

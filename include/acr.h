@@ -131,11 +131,17 @@ typedef struct {
     double setup_flops;                    /* algorithmic flops counted in setup */
     int32_t precision;
     /* with the environment variable ACR_KERNEL_TIMING=1 at setup time: the
-       H-arithmetic accumulation kernel's launch count, summed launch
+       H-arithmetic truncating kernel's launch count, summed launch
        durations (HIP events on the launch stream) and algorithmic flops */
     int32_t accum_launches;
     double accum_seconds;
     double accum_flops;
+    /* the accumulate-only first phase of every H-arithmetic step (dense
+       targets and dense sums of small low-rank targets), timed like the
+       accumulation kernel above, which then covers the truncating phase */
+    int32_t dense_launches;
+    double dense_seconds;
+    double dense_flops;
     double bytes_peak;                     /* largest device footprint reached during setup (a
                                               batched handle with several shape groups: the sum
                                               of the groups' peaks, an upper bound) */

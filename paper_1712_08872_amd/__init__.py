@@ -61,7 +61,9 @@ class Stats(ctypes.Structure):
                 ("bytes_allocated", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
                 ("setup_seconds", ctypes.c_double), ("setup_flops", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("accum_launches", ctypes.c_int32), ("accum_seconds", ctypes.c_double),
-                ("accum_flops", ctypes.c_double), ("bytes_peak", ctypes.c_double)]
+                ("accum_flops", ctypes.c_double), ("dense_launches", ctypes.c_int32),
+                ("dense_seconds", ctypes.c_double), ("dense_flops", ctypes.c_double),
+                ("bytes_peak", ctypes.c_double)]
 
     def as_dict(self):
         lv = self.levels
@@ -73,7 +75,9 @@ class Stats(ctypes.Structure):
                 "bytes_allocated": self.bytes_allocated, "bytes_per_apply": self.bytes_per_apply,
                 "setup_seconds": self.setup_seconds, "setup_flops": self.setup_flops, "precision": self.precision,
                 "accum_launches": self.accum_launches, "accum_seconds": self.accum_seconds,
-                "accum_flops": self.accum_flops, "bytes_peak": self.bytes_peak}
+                "accum_flops": self.accum_flops, "dense_launches": self.dense_launches,
+                "dense_seconds": self.dense_seconds, "dense_flops": self.dense_flops,
+                "bytes_peak": self.bytes_peak}
 
 
 SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",

@@ -18,6 +18,8 @@ SOURCES = [("k_harith.hip", ["-DKCV=64"], "k_harith_64"), ("k_harith.hip", ["-DK
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# extra compiler flags for tuning builds (e.g. ACR_HIPFLAGS="-DDENSE_WPE=5")
+FLAGS += os.environ.get("ACR_HIPFLAGS", "").split()
 
 
 def build(verbose=False, jobs=None):

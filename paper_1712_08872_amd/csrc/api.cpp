@@ -347,6 +347,9 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
     st->accum_launches += o.accum_launches;
     st->accum_seconds += o.accum_seconds;
     st->accum_flops += o.accum_flops;
+    st->dense_launches += o.dense_launches;
+    st->dense_seconds += o.dense_seconds;
+    st->dense_flops += o.dense_flops;
     st->levels = std::max(st->levels, o.levels);
   }
   return ACR_OK;

@@ -46,8 +46,8 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   if (const char* e = getenv("ACR_KERNEL_TIMING"); e && e[0] == '1') {
     timing = true;
-    d_flops = dnew<double>(1);
-    HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
+    d_flops = dnew<double>(2);
+    HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
   }
   if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
     d_prof = dnew<unsigned long long>(PS_COUNT);
@@ -132,8 +132,8 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     for (void* b : cap_pool) dfree(b);
     cap_pool.clear();
-    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, sizeof(double), s));
-    accum_launches = 0;
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
+    accum_launches = dense_launches = 0;
     ev_used = 0;
     ev_tag.clear();
     for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
@@ -158,29 +158,35 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   st.max_rank_all = maxr;
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   st.accum_launches = accum_launches;
+  st.dense_launches = dense_launches;
   if (timing) {
-    double ms = 0.0;
+    double ms = 0.0, msd = 0.0;
     for (size_t i = 0; i + 1 < ev_used; i += 2) {
       float t = 0.f;
       HIPCHK(hipEventElapsedTime(&t, ev_pool[i], ev_pool[i + 1]));
-      ms += t;
+      const bool dense = i / 2 < ev_tag.size() && ev_tag[i / 2].kernel[0] != '\0';
+      (dense ? msd : ms) += t;
     }
     st.accum_seconds = ms * 1e-3;
+    st.dense_seconds = msd * 1e-3;
     if (const char* path = getenv("ACR_TIMING_LOG"); path && path[0]) {
       // one line per accumulation launch: program, CR level, step, batch, targets, widest target, ms
       if (FILE* f = fopen(path, "w")) {
-        fprintf(f, "prog,level,step,nbatch,nt,max_m,ms\n");
+        fprintf(f, "prog,kernel,level,step,nbatch,nt,max_m,ms\n");
         for (size_t i = 0; i + 1 < ev_used && i / 2 < ev_tag.size(); i += 2) {
           float t = 0.f;
           HIPCHK(hipEventElapsedTime(&t, ev_pool[i], ev_pool[i + 1]));
           const LaunchTag& g = ev_tag[i / 2];
-          fprintf(f, "%s,%d,%d,%d,%d,%d,%.4f\n", g.prog, g.level, g.step, g.nbatch, g.nt, g.max_m, t);
+          fprintf(f, "%s,%s,%d,%d,%d,%d,%d,%.4f\n", g.prog, g.kernel, g.level, g.step, g.nbatch, g.nt, g.max_m, t);
         }
         fclose(f);
       }
     }
-    HIPCHK(hipMemcpy(&st.accum_flops, d_flops, sizeof(double), hipMemcpyDeviceToHost));
-    st.setup_flops = st.accum_flops;
+    double fl[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpy(fl, d_flops, sizeof(fl), hipMemcpyDeviceToHost));
+    st.accum_flops = fl[0];
+    st.dense_flops = fl[1];
+    st.setup_flops = fl[0] + fl[1];
   }
   if (d_prof) {
     unsigned long long pc[PS_COUNT];

@@ -77,6 +77,11 @@ struct AccumArgs {
   int64_t scratch_stride;
   double eps;
   int32_t* flags;
+  // two-phase steps: dense accumulators of small low-rank targets, filled
+  // by the accumulate-only kernel and compressed by the truncating one
+  T* dbuf;
+  const int64_t* doff;         // per target (-1: none)
+  int64_t dstride;             // per batch item
   unsigned long long* prof;    // optional cycle counters (null = off)
   double* flops;               // optional algorithmic flop counter (null = off)
 };

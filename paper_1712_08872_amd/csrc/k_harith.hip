@@ -116,6 +116,16 @@ struct Lds {
   double flops;          // algorithmic flops of the current item (thread 0)
 };
 
+// LDS of the accumulate-only kernel: the staging tiles of the piece
+// products only (no truncation workspace).
+template <typename CT>
+struct LdsPiece {
+  CT S0[KC * LDM];
+  CT S1[KC * LDM];
+  CT S2[KC * LDM];
+  double flops;
+};
+
 #define FLOP(L_, x_)                        \
   do {                                      \
     if (threadIdx.x == 0) (L_).flops += (double)(x_); \
@@ -665,9 +675,9 @@ __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const typename C
 //   LRY: V part = V_y (window columns); U part on the window rows =
 //        alpha lam U_y, i.e. alpha U_l (V_l^T U_y) for a low-rank lam.
 // Returns false when the piece does not qualify (the general path runs).
-template <typename T>
+template <typename T, typename LT>
 __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& x,
-                           const LeafRef<T>& xr, int yi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+                           const LeafRef<T>& xr, int yi, int j0, int take, T* Us, T* Vs, int K, LT& L) {
   using CT = typename CompT<T>::type;
   CT* S0c = reinterpret_cast<CT*>(L.S0);
   CT* S1c = reinterpret_cast<CT*>(L.S1);
@@ -740,9 +750,9 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
   return true;
 }
 
-template <typename T>
+template <typename T, typename LT>
 __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& tc, const DLeaf& y,
-                           const LeafRef<T>& yr, int xi, int j0, int take, T* Us, T* Vs, int K, Lds& L) {
+                           const LeafRef<T>& yr, int xi, int j0, int take, T* Us, T* Vs, int K, LT& L) {
   using CT = typename CompT<T>::type;
   CT* S0c = reinterpret_cast<CT*>(L.S0);
   CT* S1c = reinterpret_cast<CT*>(L.S1);
@@ -818,9 +828,9 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
 // of Us (target rows) and Vs (target columns), row-major ld KC.  The alpha
 // of the piece is folded into Us.  LDS buffers S0 (products), S1, S2
 // (staging) are used.
-template <typename T>
+template <typename T, typename LT>
 __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0, int take,
-                              T* Us, T* Vs, int K, Lds& L) {
+                              T* Us, T* Vs, int K, LT& L) {
   using CT = typename CompT<T>::type;
   CT* S0c = reinterpret_cast<CT*>(L.S0);
   CT* S1c = reinterpret_cast<CT*>(L.S1);
@@ -997,8 +1007,8 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
 }
 
 // Dense target: C += Us Vs^T for `take` columns (C column-major m x n).
-template <typename T>
-__device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, Lds& L) {
+template <typename T, typename LT>
+__device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, LT& L) {
   using CT = typename CompT<T>::type;
   CT* S0c = reinterpret_cast<CT*>(L.S0);
   CT* S1c = reinterpret_cast<CT*>(L.S1);
@@ -1033,9 +1043,9 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
 // leading dimension tc.m).  Low-rank pieces are expanded `take` columns at a
 // time into the staging columns [0, take) of Us / Vs and added as outer
 // products.
-template <typename T>
+template <typename T, typename LT>
 __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
-                             Lds& L) {
+                             LT& L) {
   using CT = typename CompT<T>::type;
   CT* S0c = reinterpret_cast<CT*>(L.S0);
   CT* S1c = reinterpret_cast<CT*>(L.S1);
@@ -1116,10 +1126,12 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
   if (tid == 0) L.flops = 0.0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
-    const Target tg = A.targets[A.t0 + item % A.nt];
+    const int t = A.t0 + item % A.nt;
+    const Target tg = A.targets[t];
     const int ci = inst_of(A, b, tg.crole);
     if (ci < 0) continue;
     const DLeaf tc = A.leaves[tg.cleaf];
+    if (tc.fmt == 0) continue;  // dense targets: the accumulate-only kernel
     if (A.inst_off[ci]) {  // targets are working instances (capacity layout)
       if (tid == 0) atomicOr(&A.flags[FL_LAYOUT], 1);
       continue;
@@ -1128,12 +1140,10 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
     T* Vs = Us + (int64_t)tc.m * KC;
     PROF_ADD(PS_ITEMS, 1);
     PROF_ADD(PS_NPIECES, tg.p1 - tg.p0);
-    const long long t_item = clock64();
-    const bool lr = tc.fmt != 0;
     int32_t* rk = &A.inst_rank[ci][tg.cleaf];
     T* Uc = C;
     T* Vc = C + (int64_t)tc.m * tc.cap;
-    if (lr && tg.direct) {  // exact scaled copy of a low-rank leaf
+    if (tg.direct) {  // exact scaled copy of a low-rank leaf
       const Piece P = A.pieces[tg.p0];
       const int si = inst_of(A, b, P.xrole);
       const int ks = si < 0 ? 0 : rank_of(A, si, P.xleaf);
@@ -1157,38 +1167,17 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
       __syncthreads();
       continue;
     }
-    const int k0 = (lr && tg.beta) ? *rk : 0;
+    const int k0 = tg.beta ? *rk : 0;
     // Small low-rank targets that receive more columns than their smaller
-    // dimension are accumulated exactly as a dense m x n block and
-    // compressed once: fewer recompressions, and the sum is truncated only
-    // at the end.
+    // dimension were summed exactly as a dense m x n block by the
+    // accumulate-only kernel (the same decision); here they are compressed.
     if (tid == 0) L.ival[5] = 0;
     __syncthreads();
-    if (lr && tc.m * tc.n <= DACC_MAX)
+    if (A.doff[t] >= 0)
       for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&L.ival[5], piece_width(A, b, A.pieces[p]));
     __syncthreads();
-    const bool dacc = lr && tc.m * tc.n <= DACC_MAX && L.ival[5] > imin(tc.m, tc.n);
-    T* D = lr ? Us + (int64_t)(tc.m + tc.n) * KC : C;  // dense accumulator, m x n column-major
-    if (!lr || dacc) {
-      if (lr) {
-        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
-          const int i = idx % tc.m, c = idx / tc.m;
-          double v = 0.0;
-          for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
-          D[idx] = (T)v;
-        }
-        FLOP(L, 2.0 * tc.m * tc.n * k0);
-      } else if (!tg.beta) {
-        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) D[idx] = (T)0;
-      }
-      __syncthreads();
-      dense_pieces(A, b, tg, tc, D, Us, Vs, L);
-      if (!lr) {
-        PROF_ADD(PS_DENSE, clock64() - t_item);
-        continue;
-      }
-      PROF_ADD(PS_DACC, clock64() - t_item);
-    }
+    const bool dacc = A.doff[t] >= 0 && L.ival[5] > imin(tc.m, tc.n);
+    const T* D = dacc ? A.dbuf + (int64_t)b * A.dstride + A.doff[t] : nullptr;
     // ---------------- low-rank target: columns appended in rounds of ROUND
     // beyond the current rank, recompressed in between (the cost of a
     // recompression grows with the cube of its width).  The columns come
@@ -1273,11 +1262,83 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
   if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
 }
 
+// The accumulate-only kernel needs only the staging tiles (FP32 tiles for
+// FP32 factors): with narrow rounds, trade a little spilling for six
+// resident wavefronts per SIMD (measured best among 4, 5, 6).
+#if KCV <= 40
+#ifndef DENSE_WPE
+#define DENSE_WPE 6
+#endif
+#define DENSE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(DENSE_WPE, DENSE_WPE)))
+#else
+#define DENSE_OCCUPANCY
+#endif
+// Accumulate-only first phase of a step: every dense target, and the dense
+// sum of every small low-rank target that is summed densely (same decision
+// as the truncating kernel, which then compresses it).  No truncation
+// workspace: a small LDS footprint, more resident blocks.
+template <typename T>
+__global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumArgs<T> A) {
+  __shared__ LdsPiece<typename CompT<T>::type> L;
+  __shared__ int wsum;
+  const int tid = threadIdx.x;
+  const int total = A.nbatch * A.nt;
+  T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
+  if (tid == 0) L.flops = 0.0;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int b = item / A.nt;
+    const int t = A.t0 + item % A.nt;
+    const Target tg = A.targets[t];
+    const int ci = inst_of(A, b, tg.crole);
+    if (ci < 0) continue;
+    const DLeaf tc = A.leaves[tg.cleaf];
+    if (tc.fmt != 0 && (tg.direct || A.doff[t] < 0)) continue;
+    if (A.inst_off[ci]) {
+      if (tid == 0) atomicOr(&A.flags[FL_LAYOUT], 1);
+      continue;
+    }
+    T* C = leaf_base(A, ci, tg.cleaf);
+    T* Vs = Us + (int64_t)tc.m * KC;
+    if (tc.fmt == 0) {
+      if (!tg.beta)
+        for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
+      __syncthreads();
+      dense_pieces(A, b, tg, tc, C, Us, Vs, L);
+      continue;
+    }
+    if (tid == 0) wsum = 0;
+    __syncthreads();
+    for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&wsum, piece_width(A, b, A.pieces[p]));
+    __syncthreads();
+    if (!(wsum > imin(tc.m, tc.n))) continue;
+    T* D = A.dbuf + (int64_t)b * A.dstride + A.doff[t];
+    const int k0 = tg.beta ? A.inst_rank[ci][tg.cleaf] : 0;
+    const T* Uc = C;
+    const T* Vc = C + (int64_t)tc.m * tc.cap;
+    for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+      const int i = idx % tc.m, c = idx / tc.m;
+      double v = 0.0;
+      for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
+      D[idx] = (T)v;
+    }
+    FLOP(L, 2.0 * tc.m * tc.n * k0);
+    __syncthreads();
+    dense_pieces(A, b, tg, tc, D, Us, Vs, L);
+  }
+  if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
+}
+
 // ------------------------------------------------------------ launchers
 template <typename T>
 void launch_accum(const AccumArgs<T>& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL(accum_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
 }
+template <typename T>
+void launch_accum_dense(const AccumArgs<T>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(accum_dense_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
+}
+template void launch_accum_dense<double>(const AccumArgs<double>&, int, hipStream_t);
+template void launch_accum_dense<float>(const AccumArgs<float>&, int, hipStream_t);
 template void launch_accum<double>(const AccumArgs<double>&, int, hipStream_t);
 template void launch_accum<float>(const AccumArgs<float>&, int, hipStream_t);
 

@@ -15,6 +15,7 @@ struct Step {
   int t0, nt;
   int leaf;
   int max_m, max_n;  // largest target dimensions (scratch sizing)
+  int64_t dstride = 0;  // elements of dense accumulators per batch item
 };
 
 struct Program {
@@ -26,6 +27,10 @@ struct Program {
   Piece* d_pieces = nullptr;
   Target* d_targets = nullptr;
   int32_t* d_lists = nullptr;
+  // per target: offset of its dense accumulator within its step's per-item
+  // region (small low-rank targets that may be summed densely), else -1
+  std::vector<int64_t> doff;
+  int64_t* d_doff = nullptr;
   int max_m = 0, max_n = 0;
   std::string name;
 };

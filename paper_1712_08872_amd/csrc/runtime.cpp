@@ -194,10 +194,107 @@ void Handle::sync_tables() {
 
 // ------------------------------------------------------------ programs
 void Handle::upload_program(Program& p) {
+  // dense accumulators of the small low-rank targets, per step and batch item
+  p.doff.assign(p.targets.size(), -1);
+  for (Step& st : p.steps) {
+    if (st.type != 0) continue;
+    int64_t acc = 0;
+    for (int t = st.t0; t < st.t0 + st.nt; ++t) {
+      const Target& T = p.targets[t];
+      const Leaf& L = G.lf[T.cleaf];
+      if (L.fmt == LF_LR && (int64_t)L.m * L.n <= DACC_ELEMS && !T.direct && T.p1 > T.p0) {
+        p.doff[t] = acc;
+        acc += ((int64_t)L.m * L.n + 63) / 64 * 64;
+      }
+    }
+    st.dstride = acc;
+  }
   p.d_pieces = upload(p.pieces);
   p.d_targets = upload(p.targets);
   p.d_lists = upload(p.lists);
+  p.d_doff = upload(p.doff);
 }
+
+template <typename T>
+void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, hipStream_t s) {
+  // batch chunks whose dense accumulators fit the buffer limit
+  constexpr size_t kDbufMax = size_t(4) << 30;
+  int chunk = nbatch;
+  if (st.dstride > 0) {
+    const size_t per = (size_t)st.dstride * sizeof(T);
+    chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nbatch, (int64_t)(kDbufMax / per)));
+    const size_t need = per * (size_t)chunk;
+    if (need > dbuf_bytes) {
+      if (dbuf) dfree(dbuf);
+      dbuf = dmalloc(need);
+      dbuf_bytes = need;
+    }
+  }
+  for (int b0 = 0; b0 < nbatch; b0 += chunk) {
+    const int nb = std::min(chunk, nbatch - b0);
+    AccumArgs<T> a{};
+    a.leaves = d_leaves;
+    a.pieces = P.d_pieces;
+    a.targets = P.d_targets;
+    a.lists = P.d_lists;
+    a.t0 = st.t0;
+    a.nt = st.nt;
+    a.nbatch = nb;
+    a.nroles = nroles;
+    a.nvroles = nvroles;
+    a.role_inst = d_roles + (size_t)b0 * nroles;
+    a.vec_ptr = nvroles > 0 ? d_vecs + (size_t)b0 * nvroles : nullptr;
+    a.inst_base = (T* const*)d_inst_base;
+    a.inst_rank = d_inst_rank;
+    a.inst_off = d_inst_off;
+    a.scratch = (T*)scratch;
+    a.scratch_stride = scratch_stride;
+    a.eps = opt.eps;
+    a.flags = d_flags;
+    a.dbuf = (T*)dbuf;
+    a.doff = P.d_doff;
+    a.dstride = st.dstride;
+    a.prof = d_prof;
+    a.flops = d_flops;
+    const int64_t items = (int64_t)nb * st.nt;
+    const int grid = (int)std::min<int64_t>(items, scratch_slots);
+    auto timed = [&](auto&& launch, const char* tag_suffix) {
+      if (timing) {
+        while (ev_pool.size() < ev_used + 2) {
+          hipEvent_t e;
+          HIPCHK(hipEventCreate(&e));
+          ev_pool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+        ev_tag.push_back({P.name.c_str(), cur_level, (int)(&st - P.steps.data()), nb, st.nt, st.max_m,
+                          tag_suffix});
+      }
+      launch();
+      if (timing) {
+        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
+        ev_used += 2;
+      }
+    };
+    AccumArgs<T> ad = a;
+    ad.flops = d_flops ? d_flops + 1 : nullptr;
+    timed([&] {
+      if (kc == 38)
+        kc38::launch_accum_dense<T>(ad, grid, s);
+      else
+        kc64::launch_accum_dense<T>(ad, grid, s);
+    }, "dense");
+    ++dense_launches;
+    timed([&] {
+      if (kc == 38)
+        kc38::launch_accum<T>(a, grid, s);
+      else
+        kc64::launch_accum<T>(a, grid, s);
+    }, "");
+    ++accum_launches;
+  }
+}
+template void Handle::run_accum_step<float>(Program&, const Step&, int, int, int, hipStream_t);
+template void Handle::run_accum_step<double>(Program&, const Step&, int, int, int, hipStream_t);
 
 Program& Handle::get_program(const std::string& key) {
   auto it = prog.find(key);
@@ -267,89 +364,10 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
         launch_leaf_inverse<double>((double* const*)d_inst_base, d_roles, nroles, nbatch, L.off, L.m, d_flags, s);
       continue;
     }
-    int64_t items = (int64_t)nbatch * st.nt;
-    int grid = (int)std::min<int64_t>(items, scratch_slots);
-    if (fp32) {
-      AccumArgs<float> a{};
-      a.leaves = d_leaves;
-      a.pieces = P.d_pieces;
-      a.targets = P.d_targets;
-      a.lists = P.d_lists;
-      a.t0 = st.t0;
-      a.nt = st.nt;
-      a.nbatch = nbatch;
-      a.nroles = nroles;
-      a.nvroles = nvroles;
-      a.role_inst = d_roles;
-      a.vec_ptr = d_vecs;
-      a.inst_base = (float* const*)d_inst_base;
-      a.inst_rank = d_inst_rank;
-      a.inst_off = d_inst_off;
-      a.scratch = (float*)scratch;
-      a.scratch_stride = scratch_stride;
-      a.eps = opt.eps;
-      a.flags = d_flags;
-      a.prof = d_prof;
-      a.flops = d_flops;
-      if (timing) {
-        while (ev_pool.size() < ev_used + 2) {
-          hipEvent_t e;
-          HIPCHK(hipEventCreate(&e));
-          ev_pool.push_back(e);
-        }
-        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
-        ev_tag.push_back({P.name.c_str(), cur_level, (int)si, nbatch, st.nt, st.max_m});
-      }
-      if (kc == 38)
-        kc38::launch_accum<float>(a, grid, s);
-      else
-        kc64::launch_accum<float>(a, grid, s);
-      if (timing) {
-        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
-        ev_used += 2;
-      }
-      ++accum_launches;
-    } else {
-      AccumArgs<double> a{};
-      a.leaves = d_leaves;
-      a.pieces = P.d_pieces;
-      a.targets = P.d_targets;
-      a.lists = P.d_lists;
-      a.t0 = st.t0;
-      a.nt = st.nt;
-      a.nbatch = nbatch;
-      a.nroles = nroles;
-      a.nvroles = nvroles;
-      a.role_inst = d_roles;
-      a.vec_ptr = d_vecs;
-      a.inst_base = (double* const*)d_inst_base;
-      a.inst_rank = d_inst_rank;
-      a.inst_off = d_inst_off;
-      a.scratch = (double*)scratch;
-      a.scratch_stride = scratch_stride;
-      a.eps = opt.eps;
-      a.flags = d_flags;
-      a.prof = d_prof;
-      a.flops = d_flops;
-      if (timing) {
-        while (ev_pool.size() < ev_used + 2) {
-          hipEvent_t e;
-          HIPCHK(hipEventCreate(&e));
-          ev_pool.push_back(e);
-        }
-        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
-        ev_tag.push_back({P.name.c_str(), cur_level, (int)si, nbatch, st.nt, st.max_m});
-      }
-      if (kc == 38)
-        kc38::launch_accum<double>(a, grid, s);
-      else
-        kc64::launch_accum<double>(a, grid, s);
-      if (timing) {
-        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
-        ev_used += 2;
-      }
-      ++accum_launches;
-    }
+    if (fp32)
+      run_accum_step<float>(P, st, nbatch, nroles, nvroles, s);
+    else
+      run_accum_step<double>(P, st, nbatch, nroles, nvroles, s);
   }
   HIPCHK(hipGetLastError());
 }

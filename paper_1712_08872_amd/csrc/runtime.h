@@ -31,9 +31,11 @@ struct AcrError : std::runtime_error {
 // kernel launchers (the accumulation kernel exists for round widths 38 and 64)
 namespace kc38 {
 template <typename T> void launch_accum(const AccumArgs<T>&, int grid, hipStream_t);
+template <typename T> void launch_accum_dense(const AccumArgs<T>&, int grid, hipStream_t);
 }
 namespace kc64 {
 template <typename T> void launch_accum(const AccumArgs<T>&, int grid, hipStream_t);
+template <typename T> void launch_accum_dense(const AccumArgs<T>&, int grid, hipStream_t);
 }
 template <typename T>
 void launch_leaf_inverse(T* const*, const int32_t*, int stride, int ninst, int64_t off, int m, int32_t* flags,
@@ -172,19 +174,23 @@ struct Handle {
   int64_t scratch_stride = 0;
   int scratch_slots = 0;
   int kc = 64;                 // round width of the accumulation kernel in use
+  void* dbuf = nullptr;        // dense accumulators of a two-phase step (chunk of batch items)
+  size_t dbuf_bytes = 0;
   int32_t* d_flags = nullptr;
   unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
-  double* d_flops = nullptr;             // optional algorithmic flop counter (ACR_KERNEL_TIMING=1)
+  double* d_flops = nullptr;             // optional algorithmic flop counters (ACR_KERNEL_TIMING=1):
+                                         // [0] truncating kernel, [1] accumulate-only kernel
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   struct LaunchTag {
     const char* prog;
     int level, step, nbatch, nt, max_m;
+    const char* kernel;  // "dense": accumulate-only kernel, "": truncating kernel
   };
   std::vector<LaunchTag> ev_tag;  // one per timed launch (ACR_KERNEL_TIMING=1)
   int cur_level = -1;
-  int accum_launches = 0;
+  int accum_launches = 0, dense_launches = 0;
   int32_t* d_roles = nullptr;
   int roles_cap = 0;
   const double** d_vecs = nullptr;
@@ -207,6 +213,8 @@ struct Handle {
   void free_factors();
   void run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
                    const std::vector<const double*>& vecs, hipStream_t s);
+  template <typename T>
+  void run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, hipStream_t s);
   void build_apply_jobs();
   // z_p = M_p^{-1} r_p (or M_p^{-T}) for every problem (prob < 0) or one
   void apply(const std::vector<const double*>& r, const std::vector<double*>& z, bool transpose, int prob,
