@@ -27,9 +27,11 @@
 namespace acr {
 
 static std::vector<int> initial_caps(const acr_options& o, int depth) {
+  // a caller-given max_rank is the cap itself; the automatic capacity is
+  // 6 + 6 log10(1/eps), at least 8
   int c = o.max_rank;
-  if (c <= 0) c = (int)std::lround(6.0 + 6.0 * std::log10(1.0 / o.eps));
-  c = std::max(8, std::min(KC_MAX - 8, c));
+  if (c <= 0) c = std::max(8, (int)std::lround(6.0 + 6.0 * std::log10(1.0 / o.eps)));
+  c = std::max(1, std::min(KC_MAX - 8, c));
   return std::vector<int>(depth + 1, c);
 }
 
