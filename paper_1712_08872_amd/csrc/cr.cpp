@@ -239,7 +239,11 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     // coefficient kernel order: low-rank leaves by the lane-group class of
     // the factor length it reduces over (n for V^T x, m for U^T x)
     auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6], int32_t& w4) {
-      auto cl = [](int len) { return len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : len <= 128 ? 3 : 4; };
+      // elements per lane of the coefficient kernel: 4 (FP64 factors) or 8 (FP32)
+      const int e = fp32 ? 8 : 4;
+      auto cl = [e](int len) {
+        return len <= 4 * e ? 0 : len <= 8 * e ? 1 : len <= 16 * e ? 2 : len <= 32 * e ? 3 : 4;
+      };
       std::vector<int32_t> v(lrl);
       std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
         return cl(use_m ? G.lf[a].m : G.lf[a].n) < cl(use_m ? G.lf[b].m : G.lf[b].n);

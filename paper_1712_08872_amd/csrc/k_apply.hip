@@ -60,14 +60,44 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
+// Elements of a factor column per lane in the coefficient kernel: one
+// 16-byte quad for FP64 factors, two for FP32 ones.
+template <typename T>
+struct Epl {
+  static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+};
+
+// The lane's E consecutive elements of a column starting at row r0 < len
+// (16-byte aligned; quads past len are not read) and the matching x.
+template <typename T>
+__device__ __forceinline__ double lane_dot(const T* col, const double* x, int r0, int len) {
+  constexpr int E = Epl<T>::value;
+  double v[E];
+  load4(col + r0, v);
+  if (E == 8) {
+    if (r0 + 4 < len) {
+      load4(col + r0 + 4, v + 4);
+    } else {
+#pragma unroll
+      for (int e = 4; e < E; ++e) v[e] = 0.0;
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (r0 + e < len) s += v[e] * x[r0 + e];
+  return s;
+}
+
 // s = V^T x (or U^T x) for every low-rank leaf of a job term.  The leaves
 // are ordered by the class of the length len they reduce over; a leaf of
-// class c gets a group of G = 4 << c lanes (a 16-byte quad of each column
-// per lane), so a wavefront works on 64 / G leaves at once (1 or 4 rounds),
-// with the column loads of a leaf in flight together; each column is
-// reduced within its lane group.
+// class c gets a group of G = 4 << c lanes (E = 4 consecutive elements of
+// each column per lane for FP64 factors, 8 for FP32), so a wavefront works
+// on 64 / G leaves at once (1 or 4 rounds), with the column loads of a leaf
+// in flight together; each column is reduced within its lane group.
 template <typename T>
 __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
+  constexpr int E = Epl<T>::value;
   const int lane = threadIdx.x & 63;
   const int W = A.cw[5];
   const int64_t nitems = (int64_t)A.nterms * W;
@@ -99,13 +129,7 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
         const T* f = F + (int64_t)a * ld;
         double s = 0.0;
 #pragma unroll 4
-        for (int r0 = 4 * lane; r0 < len; r0 += 256) {
-          double v[4];
-          load4(f + r0, v);
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (r0 + e < len) s += v[e] * x[r0 + e];
-        }
+        for (int r0 = E * lane; r0 < len; r0 += 64 * E) s += lane_dot(f, x, r0, len);
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) out[a] = s;
       }
@@ -123,19 +147,28 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
       const int len = A.trans ? L.m : L.n, ld = A.trans ? ldu : ldv;
       const double* x = tm.x + (A.trans ? L.r0 : L.c0);
       double* out = coef + A.soff[l];
-      if (len <= 4 * G) {  // one quad per lane and column: x once, the columns' loads together
-        const int r0 = 4 * q;
-        double xv[4];
+      if (len <= E * G) {  // one lane segment per column: x once, the columns' loads together
+        const int r0 = E * q;
+        double xv[E];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
-        const bool act = r0 < len;
+        for (int e = 0; e < E; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
+        const bool act = r0 < len, act2 = E == 8 && r0 + 4 < len;
 #pragma unroll 4
         for (int a = 0; a < k; ++a) {
           double s = 0.0;
           if (act) {
-            double v[4];
+            double v[E];
             load4(F + (int64_t)a * ld + r0, v);
-            s = v[0] * xv[0] + v[1] * xv[1] + v[2] * xv[2] + v[3] * xv[3];
+            if (E == 8) {
+              if (act2) {
+                load4(F + (int64_t)a * ld + r0 + 4, v + 4);
+              } else {
+#pragma unroll
+                for (int e = 4; e < E; ++e) v[e] = 0.0;
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) s += v[e] * xv[e];
           }
           for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
           if (q == 0) out[a] = s;
@@ -145,13 +178,7 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
           const T* f = F + (int64_t)a * ld;
           double s = 0.0;
 #pragma unroll 4
-          for (int r0 = 4 * q; r0 < len; r0 += 4 * G) {
-            double v[4];
-            load4(f + r0, v);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (r0 + e < len) s += v[e] * x[r0 + e];
-          }
+          for (int r0 = E * q; r0 < len; r0 += E * G) s += lane_dot(f, x, r0, len);
           for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
           if (q == 0) out[a] = s;
         }
