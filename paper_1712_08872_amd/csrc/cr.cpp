@@ -314,7 +314,8 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       if (scratch) dfree(scratch);
       scratch_slots = 2048;
       scratch_stride = stride;
-      scratch = dmalloc((size_t)scratch_slots * stride * (fp32 ? 4 : 8));
+      // two regions: the main stream's and the second stream's launches
+      scratch = dmalloc((size_t)2 * scratch_slots * stride * (fp32 ? 4 : 8));
     }
   }
 

@@ -82,6 +82,8 @@ struct AccumArgs {
   T* dbuf;
   const int64_t* doff;         // per target (-1: none)
   int64_t dstride;             // per batch item
+  int32_t mode;                // truncating kernel: 0 every low-rank target, 1 all but the dense
+                               // sums, 2 the dense sums only
   unsigned long long* prof;    // optional cycle counters (null = off)
   double* flops;               // optional algorithmic flop counter (null = off)
 };

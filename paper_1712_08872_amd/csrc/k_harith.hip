@@ -2,18 +2,27 @@
 // products into H-matrix leaves with truncation, dense leaf inversion and
 // the level-0 conversion of the plane operators.
 //
+// A step of formatted H-arithmetic (a product or a stage of the recursive
+// inverse, expanded on the host into targets and pieces) runs as two
+// launches over (batch item x target): accum_dense_kernel sums every dense
+// target and, exactly, every small low-rank target that receives more
+// columns than its smaller dimension; accum_kernel then compresses those
+// dense sums and builds the other low-rank targets by appending piece
+// columns and recompressing every ROUND columns.
+//
 // Truncation T_eps (Sec. 3.1.5, Sec. 4.3 of the paper: block-wise relative
 // accuracy, singular values sigma_i > eps sigma_1 kept) of a block given as
 // U V^T with K columns (the block's current factors concatenated with the
 // incoming contributions): the column pairs are norm-balanced, the Gram
 // matrices G_U = U^T U and G_V = V^T V are formed in FP64, each is factored
 // by Cholesky with symmetric pivoting, stopped at its numerical rank
-// (G = P R^T R P^T, so U = Q_U R_U P^T with Q_U = U_piv R_U11^-1), the small
-// core R_U P_U^T P_V R_V^T is diagonalised by one-sided (Hestenes) Jacobi,
-// and U' = Q_U W_k S_k, V' = Q_V Z_k are formed by triangular solves and one
-// product with the concatenated factors.  This is the truncated SVD of
-// U V^T; through the Gram matrices it resolves singular values down to
-// about 1e-8 sigma_1.
+// (G = P R^T R P^T, so U = Q_U R_U P^T with Q_U = U_piv R_U11^-1); the
+// small core C = R_U P_U^T P_V R_V^T is reduced by Cholesky with symmetric
+// pivoting of C^T C at (0.01 eps)^2 of its largest diagonal, the rest
+// diagonalised by one-sided (Hestenes) Jacobi, and U' = Q_U W_k S_k,
+// V' = Q_V Z_k are formed by triangular solves and one product with the
+// concatenated factors.  This is the truncated SVD of U V^T; through the
+// Gram matrices it resolves singular values down to about 1e-8 sigma_1.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -1144,6 +1153,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
     T* Uc = C;
     T* Vc = C + (int64_t)tc.m * tc.cap;
     if (tg.direct) {  // exact scaled copy of a low-rank leaf
+      if (A.mode == 2) continue;
       const Piece P = A.pieces[tg.p0];
       const int si = inst_of(A, b, P.xrole);
       const int ks = si < 0 ? 0 : rank_of(A, si, P.xleaf);
@@ -1177,6 +1187,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
       for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&L.ival[5], piece_width(A, b, A.pieces[p]));
     __syncthreads();
     const bool dacc = A.doff[t] >= 0 && L.ival[5] > imin(tc.m, tc.n);
+    if ((A.mode == 1 && dacc) || (A.mode == 2 && !dacc)) continue;
     const T* D = dacc ? A.dbuf + (int64_t)b * A.dstride + A.doff[t] : nullptr;
     // ---------------- low-rank target: columns appended in rounds of ROUND
     // beyond the current rank, recompressed in between (the cost of a
@@ -1299,11 +1310,14 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
     }
     T* C = leaf_base(A, ci, tg.cleaf);
     T* Vs = Us + (int64_t)tc.m * KC;
+    unsigned long long* prof = A.prof;
+    const long long t_item = clock64();
     if (tc.fmt == 0) {
       if (!tg.beta)
         for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
       __syncthreads();
       dense_pieces(A, b, tg, tc, C, Us, Vs, L);
+      PROF_ADD(PS_DENSE, clock64() - t_item);
       continue;
     }
     if (tid == 0) wsum = 0;
@@ -1324,6 +1338,7 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
     FLOP(L, 2.0 * tc.m * tc.n * k0);
     __syncthreads();
     dense_pieces(A, b, tg, tc, D, Us, Vs, L);
+    PROF_ADD(PS_DACC, clock64() - t_item);
   }
   if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
 }

@@ -59,6 +59,12 @@ void Handle::dfree(void* p) {
 }
 
 Handle::~Handle() {
+  if (s2) {
+    (void)hipStreamSynchronize(s2);
+    (void)hipStreamDestroy(s2);
+  }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
   if (hres) (void)hipHostFree(hres);
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (auto& o : owned) {
@@ -230,6 +236,12 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
       dbuf_bytes = need;
     }
   }
+  if (!s2) {
+    // default priority, like every stream of the library
+    HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
   for (int b0 = 0; b0 < nbatch; b0 += chunk) {
     const int nb = std::min(chunk, nbatch - b0);
     AccumArgs<T> a{};
@@ -258,39 +270,61 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
     a.flops = d_flops;
     const int64_t items = (int64_t)nb * st.nt;
     const int grid = (int)std::min<int64_t>(items, scratch_slots);
-    auto timed = [&](auto&& launch, const char* tag_suffix) {
+    auto timed = [&](hipStream_t q, auto&& launch, const char* tag_suffix) {
       if (timing) {
         while (ev_pool.size() < ev_used + 2) {
           hipEvent_t e;
           HIPCHK(hipEventCreate(&e));
           ev_pool.push_back(e);
         }
-        HIPCHK(hipEventRecord(ev_pool[ev_used], s));
+        HIPCHK(hipEventRecord(ev_pool[ev_used], q));
         ev_tag.push_back({P.name.c_str(), cur_level, (int)(&st - P.steps.data()), nb, st.nt, st.max_m,
                           tag_suffix});
       }
       launch();
       if (timing) {
-        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], s));
+        HIPCHK(hipEventRecord(ev_pool[ev_used + 1], q));
         ev_used += 2;
       }
     };
+    // The low-rank targets that do not need the first phase run on the
+    // second stream (own scratch slots) while the first phase and then the
+    // compression of its dense sums run on the main stream; joined before
+    // the next step.
+    AccumArgs<T> a1 = a;
+    a1.mode = 1;
+    a1.scratch = (T*)scratch + (int64_t)scratch_slots * scratch_stride;
+    HIPCHK(hipEventRecord(ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(s2, ev_fork, 0));
+    timed(s2, [&] {
+      if (kc == 38)
+        kc38::launch_accum<T>(a1, grid, s2);
+      else
+        kc64::launch_accum<T>(a1, grid, s2);
+    }, "");
     AccumArgs<T> ad = a;
     ad.flops = d_flops ? d_flops + 1 : nullptr;
-    timed([&] {
+    timed(s, [&] {
       if (kc == 38)
         kc38::launch_accum_dense<T>(ad, grid, s);
       else
         kc64::launch_accum_dense<T>(ad, grid, s);
     }, "dense");
     ++dense_launches;
-    timed([&] {
-      if (kc == 38)
-        kc38::launch_accum<T>(a, grid, s);
-      else
-        kc64::launch_accum<T>(a, grid, s);
-    }, "");
+    if (st.dstride > 0) {
+      AccumArgs<T> a2 = a;
+      a2.mode = 2;
+      timed(s, [&] {
+        if (kc == 38)
+          kc38::launch_accum<T>(a2, grid, s);
+        else
+          kc64::launch_accum<T>(a2, grid, s);
+      }, "");
+      ++accum_launches;
+    }
     ++accum_launches;
+    HIPCHK(hipEventRecord(ev_join, s2));
+    HIPCHK(hipStreamWaitEvent(s, ev_join, 0));
   }
 }
 template void Handle::run_accum_step<float>(Program&, const Step&, int, int, int, hipStream_t);

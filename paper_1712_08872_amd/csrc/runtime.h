@@ -174,6 +174,8 @@ struct Handle {
   int64_t scratch_stride = 0;
   int scratch_slots = 0;
   int kc = 64;                 // round width of the accumulation kernel in use
+  hipStream_t s2 = nullptr;    // second stream of a step (targets independent of the first phase)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void* dbuf = nullptr;        // dense accumulators of a two-phase step (chunk of batch items)
   size_t dbuf_bytes = 0;
   int32_t* d_flags = nullptr;
