@@ -1,7 +1,7 @@
 // Batched H-matrix-vector products for the preconditioner sweeps.
 //
-// The apply phase of ACR is "solely based on H matrix-vector
-// multiplications" (Sec. 5.3.1): each step of the forward/backward
+// The apply phase of ACR consists of H-matrix-vector products only
+// (Sec. 5.3.1): each step of the forward/backward
 // substitution multiplies every plane of a cyclic-reduction level by a
 // stored H-matrix (Dinv_i or a coupling).  A *job* computes
 //     y = base + sum_t alpha_t op_t(H_t) x_t
@@ -44,6 +44,27 @@ __device__ __forceinline__ void load4(const double* p, double* o) {
   o[3] = b.y;
 }
 
+// Four consecutive elements in the factor's own precision.
+template <typename T>
+__device__ __forceinline__ void load4raw(const T* p, T* o);
+template <>
+__device__ __forceinline__ void load4raw<float>(const float* p, float* o) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4raw<double>(const double* p, double* o) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  o[0] = a.x;
+  o[1] = a.y;
+  o[2] = b.x;
+  o[3] = b.y;
+}
+
 // lanes per column: the power of two covering ceil(len / 4) quads, <= 64
 __device__ __forceinline__ int lanes_per_col(int len) {
   int g = 1;
@@ -67,37 +88,30 @@ struct Epl {
   static constexpr int value = sizeof(T) == 4 ? 8 : 4;
 };
 
-// The lane's E consecutive elements of a column starting at row r0 < len
-// (16-byte aligned; quads past len are not read) and the matching x.
+// Columns of a leaf whose loads a lane issues together in the coefficient
+// kernel (NB x E factor values held at once).
+#ifndef ACR_COEF_NB32
+#define ACR_COEF_NB32 2
+#endif
+#ifndef ACR_COEF_NB64
+#define ACR_COEF_NB64 2
+#endif
 template <typename T>
-__device__ __forceinline__ double lane_dot(const T* col, const double* x, int r0, int len) {
-  constexpr int E = Epl<T>::value;
-  double v[E];
-  load4(col + r0, v);
-  if (E == 8) {
-    if (r0 + 4 < len) {
-      load4(col + r0 + 4, v + 4);
-    } else {
-#pragma unroll
-      for (int e = 4; e < E; ++e) v[e] = 0.0;
-    }
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < E; ++e)
-    if (r0 + e < len) s += v[e] * x[r0 + e];
-  return s;
-}
+struct CoefCols {
+  static constexpr int value = sizeof(T) == 4 ? ACR_COEF_NB32 : ACR_COEF_NB64;
+};
 
 // s = V^T x (or U^T x) for every low-rank leaf of a job term.  The leaves
 // are ordered by the class of the length len they reduce over; a leaf of
 // class c gets a group of G = 4 << c lanes (E = 4 consecutive elements of
 // each column per lane for FP64 factors, 8 for FP32), so a wavefront works
-// on 64 / G leaves at once (1 or 4 rounds), with the column loads of a leaf
-// in flight together; each column is reduced within its lane group.
+// on 64 / G leaves at once (1 or 4 rounds); a lane issues the loads of NB
+// columns together (x read once for them), and each column is reduced
+// within its lane group.
 template <typename T>
 __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
   constexpr int E = Epl<T>::value;
+  constexpr int NB = CoefCols<T>::value;
   const int lane = threadIdx.x & 63;
   const int W = A.cw[5];
   const int64_t nitems = (int64_t)A.nterms * W;
@@ -125,13 +139,52 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
       const double* x = tm.x + (A.trans ? L.r0 : L.c0);
       double* out = coef + A.soff[l];
       const int a1 = imin_(k, a0 + 4);
-      for (int a = a0; a < a1; ++a) {
-        const T* f = F + (int64_t)a * ld;
-        double s = 0.0;
-#pragma unroll 4
-        for (int r0 = E * lane; r0 < len; r0 += 64 * E) s += lane_dot(f, x, r0, len);
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (lane == 0) out[a] = s;
+      // NB columns side by side: their loads are in flight together and
+      // share the lane's slice of x
+      for (int ab = a0; ab < a1; ab += NB) {
+        const int nb = imin_(a1 - ab, NB);
+        const T* f = F + (int64_t)ab * ld;
+        double s[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) s[u] = 0.0;
+        for (int r0 = E * lane; r0 < len; r0 += 64 * E) {
+          double xv[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
+          const bool second = E == 8 && r0 + 4 < len;
+          T v[NB][E];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            if (u < nb) {
+              load4raw(f + (int64_t)u * ld + r0, v[u]);
+              if (E == 8) {
+                if (second) {
+                  load4raw(f + (int64_t)u * ld + r0 + 4, v[u] + 4);
+                } else {
+#pragma unroll
+                  for (int e = 4; e < E; ++e) v[u][e] = (T)0;
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            if (u < nb) {
+              double t = 0.0;
+#pragma unroll
+              for (int e = 0; e < E; ++e)
+                if (r0 + e < len) t += (double)v[u][e] * xv[e];
+              s[u] += t;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          for (int o = 32; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o);
+        if (lane == 0)
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+            if (u < nb) out[ab + u] = s[u];
       }
       continue;
     }
@@ -147,41 +200,46 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
       const int len = A.trans ? L.m : L.n, ld = A.trans ? ldu : ldv;
       const double* x = tm.x + (A.trans ? L.r0 : L.c0);
       double* out = coef + A.soff[l];
-      if (len <= E * G) {  // one lane segment per column: x once, the columns' loads together
-        const int r0 = E * q;
-        double xv[E];
+      // the host bins a leaf into class c only if len <= E * G: one lane
+      // segment per column, x read once, NB columns' loads together
+      const int r0 = E * q;
+      double xv[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
-        const bool act = r0 < len, act2 = E == 8 && r0 + 4 < len;
-#pragma unroll 4
-        for (int a = 0; a < k; ++a) {
-          double s = 0.0;
-          if (act) {
-            double v[E];
-            load4(F + (int64_t)a * ld + r0, v);
+      for (int e = 0; e < E; ++e) xv[e] = (r0 + e < len) ? x[r0 + e] : 0.0;
+      const bool act = r0 < len, act2 = E == 8 && r0 + 4 < len;
+      for (int a0 = 0; a0 < k; a0 += NB) {
+        T v[NB][E];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          if (act && a0 + u < k) {
+            load4raw(F + (int64_t)(a0 + u) * ld + r0, v[u]);
             if (E == 8) {
               if (act2) {
-                load4(F + (int64_t)a * ld + r0 + 4, v + 4);
+                load4raw(F + (int64_t)(a0 + u) * ld + r0 + 4, v[u] + 4);
               } else {
 #pragma unroll
-                for (int e = 4; e < E; ++e) v[e] = 0.0;
+                for (int e = 4; e < E; ++e) v[u][e] = (T)0;
               }
             }
+          } else {
 #pragma unroll
-            for (int e = 0; e < E; ++e) s += v[e] * xv[e];
+            for (int e = 0; e < E; ++e) v[u][e] = (T)0;
           }
-          for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-          if (q == 0) out[a] = s;
         }
-      } else {
-        for (int a = 0; a < k; ++a) {
-          const T* f = F + (int64_t)a * ld;
-          double s = 0.0;
-#pragma unroll 4
-          for (int r0 = E * q; r0 < len; r0 += E * G) s += lane_dot(f, x, r0, len);
-          for (int o = G >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-          if (q == 0) out[a] = s;
+        double s[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          s[u] = 0.0;
+#pragma unroll
+          for (int e = 0; e < E; ++e) s[u] += (double)v[u][e] * xv[e];
         }
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          for (int o = G >> 1; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o);
+        if (q == 0)
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+            if (a0 + u < k) out[a0 + u] = s[u];
       }
     }
   }
@@ -210,11 +268,12 @@ __device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* i
 }
 
 // One (leaf, pass) unit of the row kernel for this lane: rows 4q..4q+3 of
-// the segment in column c of a dense leaf or of a U factor, and the weight
-// of that column (x[c] for a dense leaf, the coefficient s[c] for U).
+// the segment in column c of a dense leaf or of a U factor (raw factor
+// values), and the weight of that column (x[c] for a dense leaf, the
+// coefficient s[c] for U).
 template <typename T>
 struct RowUnit {
-  double v[4];
+  T v[4];
   double w;
 };
 
@@ -224,17 +283,30 @@ __device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c
   if (act && c < ncols) {
     const T* col = P + (int64_t)c * ldm + ro + 4 * q;
     if ((ro & 3) == 0) {
-      load4(col, u.v);
+      load4raw(col, u.v);
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) u.v[r] = (4 * q + r < R) ? (double)col[r] : 0.0;
+      for (int r = 0; r < 4; ++r) u.v[r] = (4 * q + r < R) ? col[r] : (T)0;
     }
     u.w = wp[c];
   } else {
-    u.v[0] = u.v[1] = u.v[2] = u.v[3] = 0.0;
+    u.v[0] = u.v[1] = u.v[2] = u.v[3] = (T)0;
     u.w = 0.0;
   }
 }
+
+// Units in flight per wavefront in the row kernel (a ring: the loads of the
+// next RING-1 units are issued before a unit is accumulated).
+#ifndef ACR_RING32
+#define ACR_RING32 6
+#endif
+#ifndef ACR_RING64
+#define ACR_RING64 3
+#endif
+template <typename T>
+struct RowRing {
+  static constexpr int value = sizeof(T) == 4 ? ACR_RING32 : ACR_RING64;
+};
 
 // y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi], one block per (job, row
 // segment); wavefront w takes every 4th leaf of the segment's list and the
@@ -242,10 +314,11 @@ __device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c
 // contributes its columns weighted by x, a low-rank leaf the columns of U
 // weighted by its coefficients s = V^T x; lanes map to (row quad, column)
 // with 16-byte loads when the segment starts 4-aligned inside the leaf.
-// The loads of the next (leaf, column pass) are issued before the current
-// one is accumulated.
+// The (leaf, column pass) units are walked through a ring, so the loads of
+// several units are in flight while one is accumulated.
 template <typename T>
 __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
+  constexpr int D = RowRing<T>::value;
   __shared__ double red[4][256];
   __shared__ double part[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -273,10 +346,12 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
       const double al = tm.alpha;
       for (int eb = w; eb < ne; eb += 256) {
         const int cnt = imin_(64, (ne - eb + 3) / 4);  // this wave's leaves eb, eb+4, ...
+        if (cnt <= 0) continue;
         SegDesc d{};
         if (lane < cnt) d = seg_desc(A, A.rows_idx, e0 + eb + 4 * lane, tm.inst);
-        // walk the (leaf, column pass) units with one unit of prefetch
+        // the walker: the next unit to load is column pass c0 of leaf i
         int i = 0, c0 = 0;
+        bool more = true;
         const T* P = nullptr;
         const double* wp = nullptr;
         int ldm = 0, ro = 0, ncols = 0;
@@ -288,29 +363,35 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
           ncols = fmt ? bcast(d.k, ii) : bcast(d.n, ii);
           wp = fmt ? coef + bcast64(d.so, ii) : tm.x + bcast(d.c0, ii);
         };
-        if (cnt == 0) continue;
+        int issued = 0;  // real units loaded so far (uniform)
+        auto issue = [&](RowUnit<T>& u) {
+          if (!more) {
+            u.v[0] = u.v[1] = u.v[2] = u.v[3] = (T)0;
+            u.w = 0.0;
+            return;
+          }
+          row_unit_load(P, ldm, ro, c0 + co, ncols, wp, q, R, qact, u);
+          ++issued;
+          c0 += cpp;
+          if (c0 >= ncols) {
+            c0 = 0;
+            if (++i < cnt)
+              leaf(i);
+            else
+              more = false;
+          }
+        };
         leaf(0);
-        RowUnit<T> cur, nxt;
-        row_unit_load(P, ldm, ro, co, ncols, wp, q, R, qact, cur);
-        while (true) {
-          // advance to the next unit
-          int ni = i, nc0 = c0 + cpp;
-          if (nc0 >= ncols) {
-            ni = i + 1;
-            nc0 = 0;
-          }
-          const bool more = ni < cnt;
-          if (more) {
-            if (ni != i) leaf(ni);
-            row_unit_load(P, ldm, ro, nc0 + co, ncols, wp, q, R, qact, nxt);
-          }
-          const double wc = al * cur.w;
+        RowUnit<T> u[D];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accq[r] += cur.v[r] * wc;
-          if (!more) break;
-          cur = nxt;
-          i = ni;
-          c0 = nc0;
+        for (int s = 0; s < D - 1; ++s) issue(u[s]);
+        for (int done = 0; done < issued; ++done) {
+          issue(u[D - 1]);
+          const double wc = al * u[0].w;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accq[r] += (double)u[0].v[r] * wc;
+#pragma unroll
+          for (int s = 0; s < D - 1; ++s) u[s] = u[s + 1];
         }
       }
     }
