@@ -194,7 +194,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     unsigned long long pc[PS_COUNT];
     HIPCHK(hipMemcpy(pc, d_prof, sizeof(pc), hipMemcpyDeviceToHost));
     const char* names[] = {"pieces_lr", "gram", "eig1", "eig2", "rebuild", "dense", "items", "trunc", "sweeps",
-                           "npieces", "ksum", "dacc", "lrx", "lry", "dd", "outer"};
+                           "npieces", "ksum", "dacc", "lrx", "lry", "dd", "outer", "tn", "nn"};
     fprintf(stderr, "[acr profile]");
     for (int i = 0; i < PS_COUNT; ++i) fprintf(stderr, " %s=%.4g", names[i], (double)pc[i]);
     fprintf(stderr, "\n");

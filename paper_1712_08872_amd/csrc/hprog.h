@@ -92,7 +92,7 @@ struct AccumArgs {
 enum ProfSlot : int32_t {
   PS_PIECES_LR = 0, PS_GRAM = 1, PS_EIG1 = 2, PS_EIG2 = 3, PS_REBUILD = 4, PS_DENSE = 5, PS_ITEMS = 6,
   PS_TRUNC = 7, PS_SWEEPS = 8, PS_NPIECES = 9, PS_KSUM = 10, PS_DACC = 11, PS_LRX = 12, PS_LRY = 13,
-  PS_DDP = 14, PS_OUTER = 15, PS_COUNT = 16
+  PS_DDP = 14, PS_OUTER = 15, PS_TN = 16, PS_NN = 17, PS_COUNT = 18
 };
 
 struct MvTerm {

@@ -604,51 +604,98 @@ __device__ int piece_width(const AccumArgs<T>& A, int b, const Piece& P) {
   return 0;
 }
 
+// One 16 x 16 x 4 matrix-core step in the compute type: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; element r of the lane's
+// accumulator is row row(l / 16, r), column l % 16 of the 16 x 16 tile
+// (4 (l / 16) + r for FP32, l / 16 + 4 r for FP64, as measured on gfx950).
+template <typename CT>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct Mfma16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+
 // Out[i][j] = sum_q P[q + i*ldp] * R[q + j*ldr] for i < mo, j < no (both
-// operands contiguous along q), staged through LDS in chunks of KC along q.
-// Out is LDS with leading dimension KC; mo, no <= KC.
+// operands contiguous along q) on the matrix cores: 16 x 16 output tiles,
+// the operands read straight from memory (a lane takes 4 consecutive q of
+// one column, consumed by 4 steps), 16 q per chunk.  With fewer than four
+// tiles the chunks of a tile are split over the wavefronts and the partial
+// tiles added in a fixed order in LDS (`bP`, >= 4 x 256 elements).  Out is
+// LDS with leading dimension KC; mo, no <= KC.
 template <typename T>
 __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no,
                            typename CompT<T>::type* Out, typename CompT<T>::type* bP,
-                           typename CompT<T>::type* bR) {
+                           typename CompT<T>::type* bR, unsigned long long* prof) {
   using CT = typename CompT<T>::type;
-  const int tid = threadIdx.x;
-  constexpr int PER = (KC * KC + TPB - 1) / TPB;
-  CT acc[PER];
+  using MF = Mfma16<CT>;
+  using V = typename MF::v4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const long long tp0 = clock64();
+  const int ntn = (no + 15) >> 4, nt = ((mo + 15) >> 4) * ntn;
+  const int nparts = nt >= 4 ? 1 : 4 / nt;
+  const int nchunk = (nq + 15) >> 4;
+  __syncthreads();  // the caller's last reads of Out / bP are done
+  for (int u = w; u < nt * nparts; u += TPB / 64) {
+    const int t = u % nt, part = u / nt;
+    const int ti = t / ntn, tj = t - ti * ntn;
+    const int i = ti * 16 + l16, j = tj * 16 + l16;
+    const bool ai = i < mo, bj = j < no;
+    const T* pa = P + (int64_t)i * ldp;
+    const T* pb = R + (int64_t)j * ldr;
+    V acc = {0, 0, 0, 0};
+#pragma unroll 1
+    for (int c = part; c < nchunk; c += nparts) {
+      const int q = c * 16 + 4 * g;
+      CT av[4], bv[4];
 #pragma unroll
-  for (int e = 0; e < PER; ++e) acc[e] = 0;
-  for (int q0 = 0; q0 < nq; q0 += KC) {
-    const int nqq = imin(KC, nq - q0);
-    for (int idx = tid; idx < nqq * mo; idx += TPB) {
-      const int q = idx % nqq, i = idx / nqq;
-      bP[q * KC + i] = (CT)P[q0 + q + (int64_t)i * ldp];
-    }
-    for (int idx = tid; idx < nqq * no; idx += TPB) {
-      const int q = idx % nqq, j = idx / nqq;
-      bR[q * KC + j] = (CT)R[q0 + q + (int64_t)j * ldr];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = tid + e * TPB;
-      if (idx < mo * no) {
-        const int i = idx / no, j = idx - i * no;
-        CT s = 0;
-        for (int q = 0; q < nqq; ++q) s += bP[q * KC + i] * bR[q * KC + j];
-        acc[e] += s;
+      for (int e = 0; e < 4; ++e) {
+        const bool in = q + e < nq;
+        av[e] = (ai && in) ? (CT)pa[q + e] : (CT)0;
+        bv[e] = (bj && in) ? (CT)pb[q + e] : (CT)0;
       }
-    }
-    __syncthreads();
-  }
 #pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int idx = tid + e * TPB;
-    if (idx < mo * no) {
-      const int i = idx / no, j = idx - i * no;
-      Out[i * KC + j] = acc[e];
+      for (int e = 0; e < 4; ++e) acc = MF::step(av[e], bv[e], acc);
+    }
+    if (nparts == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = ti * 16 + MF::row(g, r), jj = tj * 16 + l16;
+        if (ii < mo && jj < no) Out[ii * KC + jj] = acc[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bP[u * 256 + MF::row(g, r) * 16 + l16] = acc[r];
+    }
+  }
+  if (nparts > 1) {
+    __syncthreads();
+    // tile t's partials are units t, t + nt, ...
+    for (int idx = tid; idx < nt * 256; idx += TPB) {
+      const int t = idx >> 8, e = idx & 255;
+      const int ti = t / ntn, tj = t - ti * ntn;
+      const int ii = ti * 16 + (e >> 4), jj = tj * 16 + (e & 15);
+      if (ii < mo && jj < no) {
+        CT sum = 0;
+        for (int p = 0; p < nparts; ++p) sum += bP[(t + p * nt) * 256 + e];
+        Out[ii * KC + jj] = sum;
+      }
     }
   }
   __syncthreads();
+  PROF_ADD(PS_TN, clock64() - tp0);
 }
 
 // dst[i*drs + j*dcs] += alpha * sum_a M[i + a*ldm] * Z[a*KC + j] for i < mi,
@@ -656,7 +703,8 @@ __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int
 // an LDS staging buffer of KC x KC doubles.
 template <typename T>
 __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const typename CompT<T>::type* Z, int no, T* dst,
-                       int64_t drs, int64_t dcs, double alpha, typename CompT<T>::type* bM) {
+                       int64_t drs, int64_t dcs, double alpha, typename CompT<T>::type* bM,
+                       unsigned long long* prof) {
   using CT = typename CompT<T>::type;
   const int tid = threadIdx.x;
   for (int i0 = 0; i0 < mi; i0 += KC) {
@@ -886,7 +934,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         for (int c0 = cA; c0 < cB; c0 += KC) {
           const int nc = imin(KC, cB - c0);
           tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, S0c, S1c,
-                     S2c);
+                     S2c, A.prof);
           FLOP(L, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
@@ -900,9 +948,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c);
+        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, S0c, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
-               S1c);
+               S1c, A.prof);
         FLOP(L, 2.0 * kl * take * (nq + (cB - cA)));
       }
     }
@@ -947,7 +995,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           }
           __syncthreads();
           nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, S0c, take,
-                 Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, S1c);
+                 Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
           FLOP(L, 2.0 * (rB - rA) * nqc * take);
         }
       } else {
@@ -955,9 +1003,9 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c);
+        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, S0c, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
-               S1c);
+               S1c, A.prof);
         FLOP(L, 2.0 * kl * take * (nq + (rB - rA)));
       }
     }
@@ -986,7 +1034,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       }
       __syncthreads();
       nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, take,
-             Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, S1c);
+             Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
       FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * take);
     }
   } else {  // PK_COPY of a low-rank leaf
@@ -1015,37 +1063,43 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
   if (P.kind == PK_LRY) PROF_ADD(PS_LRY, clock64() - tpc);
 }
 
-// Dense target: C += Us Vs^T for `take` columns (C column-major m x n).
+// Dense target: C += Us Vs^T for `take` columns (C column-major m x n;
+// Us, Vs row-major with leading dimension KC): 16 x 16 tiles of C over the
+// wavefronts on the matrix cores.
 template <typename T, typename LT>
 __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, LT& L) {
   using CT = typename CompT<T>::type;
-  CT* S0c = reinterpret_cast<CT*>(L.S0);
-  CT* S1c = reinterpret_cast<CT*>(L.S1);
-  CT* S2c = reinterpret_cast<CT*>(L.S2);
-  const int tid = threadIdx.x;
-  for (int c0 = 0; c0 < tc.n; c0 += KC) {
-    const int nc = imin(KC, tc.n - c0);
-    for (int idx = tid; idx < nc * take; idx += TPB) {
-      const int jj = idx % take, cc = idx / take;
-      S0c[jj * KC + cc] = (CT)Vs[(int64_t)(c0 + cc) * KC + jj];
+  using MF = Mfma16<CT>;
+  using V = typename MF::v4;
+  (void)L;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int m = tc.m, n = tc.n;
+  const int ntn = (n + 15) >> 4, nt = ((m + 15) >> 4) * ntn;
+  const int nk = (take + 3) >> 2;
+  for (int t = w; t < nt; t += TPB / 64) {
+    const int ti = t / ntn, tj = t - ti * ntn;
+    const int i = ti * 16 + l16, j = tj * 16 + l16;
+    const bool ai = i < m, bj = j < n;
+    V acc = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < nk; ++kk) {
+      const int k = 4 * kk + g;
+      const bool in = k < take;
+      const CT av = (ai && in) ? (CT)Us[(int64_t)i * KC + k] : (CT)0;
+      const CT bv = (bj && in) ? (CT)Vs[(int64_t)j * KC + k] : (CT)0;
+      acc = MF::step(av, bv, acc);
     }
-    for (int i0 = 0; i0 < tc.m; i0 += KC) {
-      const int ni = imin(KC, tc.m - i0);
-      for (int idx = tid; idx < ni * take; idx += TPB) {
-        const int jj = idx % take, ii = idx / take;
-        S1c[jj * KC + ii] = (CT)Us[(int64_t)(i0 + ii) * KC + jj];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = ti * 16 + MF::row(g, r), jj = tj * 16 + l16;
+      if (ii < m && jj < n) {
+        T* d = &C[ii + (int64_t)jj * m];
+        *d = (T)((CT)*d + acc[r]);
       }
-      __syncthreads();
-      for (int idx = tid; idx < ni * nc; idx += TPB) {
-        const int ii = idx % ni, cc = idx / ni;
-        CT s = 0;
-        for (int jj = 0; jj < take; ++jj) s += S1c[jj * KC + ii] * S0c[jj * KC + cc];
-        T* d = &C[(i0 + ii) + (int64_t)(c0 + cc) * tc.m];
-        *d = (T)((CT)*d + s);
-      }
-      __syncthreads();
     }
   }
+  __syncthreads();
 }
 
 // Dense accumulation C += sum of the target's pieces (C column-major,
@@ -1082,7 +1136,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
           }
           __syncthreads();
           nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, nc,
-                 C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, S1c);
+                 C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, S1c, A.prof);
           FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
         }
       }
