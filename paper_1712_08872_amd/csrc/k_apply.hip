@@ -267,38 +267,50 @@ __device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* i
   return d;
 }
 
+// Columns per unit of the row kernel: two for FP32 factors (32 bytes per
+// lane per unit, as one column of FP64 factors).
+template <typename T>
+struct RowCols {
+  static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
 // One (leaf, pass) unit of the row kernel for this lane: rows 4q..4q+3 of
-// the segment in column c of a dense leaf or of a U factor (raw factor
-// values), and the weight of that column (x[c] for a dense leaf, the
-// coefficient s[c] for U).
+// the segment in columns c + s cpp (s < NC) of a dense leaf or of a U
+// factor (raw factor values), and the weights of those columns (x for a
+// dense leaf, the coefficients s = V^T x for U).
 template <typename T>
 struct RowUnit {
-  T v[4];
-  double w;
+  static constexpr int NC = RowCols<T>::value;
+  T v[NC][4];
+  double w[NC];
 };
 
 template <typename T>
-__device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c, int ncols, const double* wp, int q,
-                                              int R, bool act, RowUnit<T>& u) {
-  if (act && c < ncols) {
-    const T* col = P + (int64_t)c * ldm + ro + 4 * q;
-    if ((ro & 3) == 0) {
-      load4raw(col, u.v);
-    } else {
+__device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c, int cpp, int ncols,
+                                              const double* wp, int q, int R, bool act, RowUnit<T>& u) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) u.v[r] = (4 * q + r < R) ? col[r] : (T)0;
+  for (int s = 0; s < RowUnit<T>::NC; ++s) {
+    const int cs = c + s * cpp;
+    if (act && cs < ncols) {
+      const T* col = P + (int64_t)cs * ldm + ro + 4 * q;
+      if ((ro & 3) == 0) {
+        load4raw(col, u.v[s]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u.v[s][r] = (4 * q + r < R) ? col[r] : (T)0;
+      }
+      u.w[s] = wp[cs];
+    } else {
+      u.v[s][0] = u.v[s][1] = u.v[s][2] = u.v[s][3] = (T)0;
+      u.w[s] = 0.0;
     }
-    u.w = wp[c];
-  } else {
-    u.v[0] = u.v[1] = u.v[2] = u.v[3] = (T)0;
-    u.w = 0.0;
   }
 }
 
 // Units in flight per wavefront in the row kernel (a ring: the loads of the
 // next RING-1 units are issued before a unit is accumulated).
 #ifndef ACR_RING32
-#define ACR_RING32 6
+#define ACR_RING32 2
 #endif
 #ifndef ACR_RING64
 #define ACR_RING64 3
@@ -366,13 +378,16 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
         int issued = 0;  // real units loaded so far (uniform)
         auto issue = [&](RowUnit<T>& u) {
           if (!more) {
-            u.v[0] = u.v[1] = u.v[2] = u.v[3] = (T)0;
-            u.w = 0.0;
+#pragma unroll
+            for (int sc = 0; sc < RowUnit<T>::NC; ++sc) {
+              u.v[sc][0] = u.v[sc][1] = u.v[sc][2] = u.v[sc][3] = (T)0;
+              u.w[sc] = 0.0;
+            }
             return;
           }
-          row_unit_load(P, ldm, ro, c0 + co, ncols, wp, q, R, qact, u);
+          row_unit_load(P, ldm, ro, c0 + co, cpp, ncols, wp, q, R, qact, u);
           ++issued;
-          c0 += cpp;
+          c0 += RowUnit<T>::NC * cpp;
           if (c0 >= ncols) {
             c0 = 0;
             if (++i < cnt)
@@ -387,9 +402,12 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
         for (int s = 0; s < D - 1; ++s) issue(u[s]);
         for (int done = 0; done < issued; ++done) {
           issue(u[D - 1]);
-          const double wc = al * u[0].w;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accq[r] += (double)u[0].v[r] * wc;
+          for (int sc = 0; sc < RowUnit<T>::NC; ++sc) {
+            const double wc = al * u[0].w[sc];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accq[r] += (double)u[0].v[sc][r] * wc;
+          }
 #pragma unroll
           for (int s = 0; s < D - 1; ++s) u[s] = u[s + 1];
         }

@@ -707,6 +707,7 @@ __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const typename C
                        unsigned long long* prof) {
   using CT = typename CompT<T>::type;
   const int tid = threadIdx.x;
+  const long long tp0 = clock64();
   for (int i0 = 0; i0 < mi; i0 += KC) {
     const int ni = imin(KC, mi - i0);
     for (int idx = tid; idx < ni * na; idx += TPB) {
@@ -723,6 +724,7 @@ __device__ void nn_acc(const T* M, int64_t ldm, int mi, int na, const typename C
     }
     __syncthreads();
   }
+  PROF_ADD(PS_NN, clock64() - tp0);
 }
 
 // One-leaf list whose overlap with the piece fits one staging tile: the
