@@ -64,9 +64,16 @@ typedef enum {
 
 typedef enum {
     ACR_FP64 = 0,       /* factors stored and multiplied in FP64 */
-    ACR_MIXED_FP32 = 1  /* factors stored and multiplied in FP32; leaf
+    ACR_MIXED_FP32 = 1, /* factors stored and multiplied in FP32; leaf
                            inversion, Gram matrices, core eigen/SVD and
                            Krylov in FP64 */
+    ACR_MIXED_BF16 = 2  /* setup as ACR_MIXED_FP32, then the stored factors
+                           are rounded to BF16 (8-bit mantissa, nearest
+                           even), halving the bytes the apply streams;
+                           apply arithmetic in FP64.  Only for eps >= 1e-2
+                           (ACR_E_INVALID otherwise): the rounding error,
+                           about 4e-3 relative per entry, must stay below
+                           the truncation accuracy */
 } acr_precision;
 
 typedef enum { ACR_CG = 0, ACR_FCG = 1, ACR_GMRES = 2 } acr_method;

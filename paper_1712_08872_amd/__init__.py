@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacr.so")
 
 POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW = 0, 1, 2, 3
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 CG, FCG, GMRES = 0, 1, 2
 MAX_LEVELS = 32
 STATUS = ["OK", "E_INVALID", "E_NUMERIC", "E_NOMEM", "E_SINGULAR", "E_BREAKDOWN", "E_NOTCONV", "E_DEVICE",

@@ -76,7 +76,10 @@ acr_status check_options(const acr_options* o) {
   if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ACR_E_INVALID, "eps must lie in (0, 1)");
   if (!finite_pos(o->eta)) return fail(ACR_E_INVALID, "eta must be positive");
   if (o->leaf_size < 4 || o->leaf_size > 64) return fail(ACR_E_INVALID, "leaf_size must lie in [4, 64]");
-  if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32) return fail(ACR_E_INVALID, "unknown precision");
+  if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32 && o->precision != ACR_MIXED_BF16)
+    return fail(ACR_E_INVALID, "unknown precision");
+  if (o->precision == ACR_MIXED_BF16 && !(o->eps >= 1e-2))
+    return fail(ACR_E_INVALID, "BF16 factors need eps >= 1e-2");
   if (o->max_rank < 0 || o->max_rank > acr::KC_MAX - 8) return fail(ACR_E_INVALID, "max_rank must lie in [0, 56]");
   if (o->dense_work < 0 || o->dense_work > 64) return fail(ACR_E_INVALID, "dense_work must lie in [0, 64]");
   if ((o->alloc == nullptr) != (o->free == nullptr)) return fail(ACR_E_INVALID, "alloc and free come together");

@@ -42,7 +42,8 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   nz = ps[0].nz;
   B = nx * ny;
   N = (int64_t)B * nz;
-  fp32 = opt.precision == ACR_MIXED_FP32;
+  fp32 = opt.precision == ACR_MIXED_FP32 || opt.precision == ACR_MIXED_BF16;
+  bf16 = opt.precision == ACR_MIXED_BF16;
   const int64_t M = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
   d_flags = dnew<int32_t>(FL_COUNT);
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
@@ -151,6 +152,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     scratch = nullptr;
     scratch_stride = 0;
   }
+  if (bf16) round_factors_bf16(s);
   build_apply_jobs();
   HIPCHK(hipStreamSynchronize(s));
   const int retries = st.retries, overflow = st.rank_overflow, maxr = st.max_rank_all;
@@ -650,78 +652,50 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
     ph = transpose ? &ph_applyT : &ph_apply;
   else
     ph = transpose ? &probs[prob].ph_applyT : &probs[prob].ph_apply;
-  for (const PhaseJobs& pj : *ph) {
-    if (fp32) {
-      MvArgs<float> a{};
-      a.leaves = d_leaves;
-      a.lr_leaves = d_lr_leaves;
-      a.soff = d_soff;
-      a.nlr = G.nlr;
-      a.sstride = sstride;
-      a.jobs = pj.d;
-      a.njobs = pj.n;
-      a.terms = pj.terms;
-      a.nterms = pj.nterms;
-      a.trans = pj.trans;
-      a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
-      {
-        // four leaves per lane group when the phase fills the chip anyway
-        const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
-        const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
-        a.rounds = ri ? 4 : 1;
-        a.w4 = pj.trans ? w4_t : w4_n;
-        for (int c = 0; c < 6; ++c) {
-          a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
-          a.cw[c] = cw[ri][c];
-        }
+  auto phase = [&](const PhaseJobs& pj, auto tag) {
+    using T = decltype(tag);
+    MvArgs<T> a{};
+    a.leaves = d_leaves;
+    a.lr_leaves = d_lr_leaves;
+    a.soff = d_soff;
+    a.nlr = G.nlr;
+    a.sstride = sstride;
+    a.jobs = pj.d;
+    a.njobs = pj.n;
+    a.terms = pj.terms;
+    a.nterms = pj.nterms;
+    a.trans = pj.trans;
+    a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
+    {
+      // four leaves per lane group when the phase fills the chip anyway
+      const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
+      const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
+      a.rounds = ri ? 4 : 1;
+      a.w4 = pj.trans ? w4_t : w4_n;
+      for (int c = 0; c < 6; ++c) {
+        a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
+        a.cw[c] = cw[ri][c];
       }
-      a.inst_base = (float* const*)d_inst_base;
-      a.inst_rank = d_inst_rank;
-      a.inst_off = d_inst_off;
-      a.coef = coef;
-      a.seg_lo = d_seg_lo;
-      a.rows_ptr = d_rows_ptr;
-      a.rows_idx = d_rows_idx;
-      a.cols_ptr = d_cols_ptr;
-      a.cols_idx = d_cols_idx;
-      a.nseg = (int)G.leaf_clusters.size();
-      launch_mv<float>(a, s);
-    } else {
-      MvArgs<double> a{};
-      a.leaves = d_leaves;
-      a.lr_leaves = d_lr_leaves;
-      a.soff = d_soff;
-      a.nlr = G.nlr;
-      a.sstride = sstride;
-      a.jobs = pj.d;
-      a.njobs = pj.n;
-      a.terms = pj.terms;
-      a.nterms = pj.nterms;
-      a.trans = pj.trans;
-      a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
-      {
-        // four leaves per lane group when the phase fills the chip anyway
-        const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
-        const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
-        a.rounds = ri ? 4 : 1;
-        a.w4 = pj.trans ? w4_t : w4_n;
-        for (int c = 0; c < 6; ++c) {
-          a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
-          a.cw[c] = cw[ri][c];
-        }
-      }
-      a.inst_base = (double* const*)d_inst_base;
-      a.inst_rank = d_inst_rank;
-      a.inst_off = d_inst_off;
-      a.coef = coef;
-      a.seg_lo = d_seg_lo;
-      a.rows_ptr = d_rows_ptr;
-      a.rows_idx = d_rows_idx;
-      a.cols_ptr = d_cols_ptr;
-      a.cols_idx = d_cols_idx;
-      a.nseg = (int)G.leaf_clusters.size();
-      launch_mv<double>(a, s);
     }
+    a.inst_base = (T* const*)d_inst_base;
+    a.inst_rank = d_inst_rank;
+    a.inst_off = d_inst_off;
+    a.coef = coef;
+    a.seg_lo = d_seg_lo;
+    a.rows_ptr = d_rows_ptr;
+    a.rows_idx = d_rows_idx;
+    a.cols_ptr = d_cols_ptr;
+    a.cols_idx = d_cols_idx;
+    a.nseg = (int)G.leaf_clusters.size();
+    launch_mv<T>(a, s);
+  };
+  for (const PhaseJobs& pj : *ph) {
+    if (bf16)
+      phase(pj, bf16s{});
+    else if (fp32)
+      phase(pj, float{});
+    else
+      phase(pj, double{});
   }
   for (int q = 0; q < np; ++q)
     if (prob < 0 || q == prob) launch_from_horder(z + (int64_t)q * N, out[q], d_perm, B, N, s);
@@ -735,7 +709,7 @@ void Handle::matvec(int prob, const double* x, double* y, bool transpose, hipStr
 
 // ------------------------------------------------------------ statistics
 double Handle::instance_bytes(const std::vector<int32_t>& rk) const {
-  const double esz = fp32 ? 4.0 : 8.0;
+  const double esz = bf16 ? 2.0 : fp32 ? 4.0 : 8.0;
   double b = 0.0;
   for (size_t l = 0; l < G.lf.size(); ++l) {
     const Leaf& L = G.lf[l];

@@ -18,8 +18,10 @@
 // FP64; the factor loads are FP32 in mixed precision.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
+#include "bf16.h"
 #include "hprog.h"
 
 namespace acr {
@@ -44,7 +46,16 @@ __device__ __forceinline__ void load4(const double* p, double* o) {
   o[3] = b.y;
 }
 
-// Four consecutive elements in the factor's own precision.
+__device__ __forceinline__ void load4(const bf16s* p, double* o) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  o[0] = (double)bf16s{(uint16_t)(v.x & 0xffffu)};
+  o[1] = (double)bf16s{(uint16_t)(v.x >> 16)};
+  o[2] = (double)bf16s{(uint16_t)(v.y & 0xffffu)};
+  o[3] = (double)bf16s{(uint16_t)(v.y >> 16)};
+}
+
+// Four consecutive elements in the factor's own precision (16-byte loads
+// for FP32 and FP64, 8-byte loads for BF16).
 template <typename T>
 __device__ __forceinline__ void load4raw(const T* p, T* o);
 template <>
@@ -54,6 +65,14 @@ __device__ __forceinline__ void load4raw<float>(const float* p, float* o) {
   o[1] = v.y;
   o[2] = v.z;
   o[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4raw<bf16s>(const bf16s* p, bf16s* o) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  o[0].b = (uint16_t)(v.x & 0xffffu);
+  o[1].b = (uint16_t)(v.x >> 16);
+  o[2].b = (uint16_t)(v.y & 0xffffu);
+  o[3].b = (uint16_t)(v.y >> 16);
 }
 template <>
 __device__ __forceinline__ void load4raw<double>(const double* p, double* o) {
@@ -81,11 +100,11 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
-// Elements of a factor column per lane in the coefficient kernel: one
-// 16-byte quad for FP64 factors, two for FP32 ones.
+// Elements of a factor column per lane in the coefficient kernel: 4 for
+// FP64 factors, 8 for FP32 and BF16 ones.
 template <typename T>
 struct Epl {
-  static constexpr int value = sizeof(T) == 4 ? 8 : 4;
+  static constexpr int value = sizeof(T) == 8 ? 4 : 8;
 };
 
 // Columns of a leaf whose loads a lane issues together in the coefficient
@@ -98,7 +117,7 @@ struct Epl {
 #endif
 template <typename T>
 struct CoefCols {
-  static constexpr int value = sizeof(T) == 4 ? ACR_COEF_NB32 : ACR_COEF_NB64;
+  static constexpr int value = sizeof(T) == 8 ? ACR_COEF_NB64 : ACR_COEF_NB32;
 };
 
 // s = V^T x (or U^T x) for every low-rank leaf of a job term.  The leaves
@@ -162,7 +181,7 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
                   load4raw(f + (int64_t)u * ld + r0 + 4, v[u] + 4);
                 } else {
 #pragma unroll
-                  for (int e = 4; e < E; ++e) v[u][e] = (T)0;
+                  for (int e = 4; e < E; ++e) v[u][e] = T{};
                 }
               }
             }
@@ -218,12 +237,12 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
                 load4raw(F + (int64_t)(a0 + u) * ld + r0 + 4, v[u] + 4);
               } else {
 #pragma unroll
-                for (int e = 4; e < E; ++e) v[u][e] = (T)0;
+                for (int e = 4; e < E; ++e) v[u][e] = T{};
               }
             }
           } else {
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[u][e] = (T)0;
+            for (int e = 0; e < E; ++e) v[u][e] = T{};
           }
         }
         double s[NB];
@@ -267,11 +286,11 @@ __device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* i
   return d;
 }
 
-// Columns per unit of the row kernel: two for FP32 factors (32 bytes per
-// lane per unit, as one column of FP64 factors).
+// Columns per unit of the row kernel: two for FP32 and BF16 factors (32
+// bytes per lane per unit for FP32, as one column of FP64 factors).
 template <typename T>
 struct RowCols {
-  static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+  static constexpr int value = sizeof(T) == 8 ? 1 : 2;
 };
 
 // One (leaf, pass) unit of the row kernel for this lane: rows 4q..4q+3 of
@@ -297,11 +316,11 @@ __device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c
         load4raw(col, u.v[s]);
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) u.v[s][r] = (4 * q + r < R) ? col[r] : (T)0;
+        for (int r = 0; r < 4; ++r) u.v[s][r] = (4 * q + r < R) ? col[r] : T{};
       }
       u.w[s] = wp[cs];
     } else {
-      u.v[s][0] = u.v[s][1] = u.v[s][2] = u.v[s][3] = (T)0;
+      u.v[s][0] = u.v[s][1] = u.v[s][2] = u.v[s][3] = T{};
       u.w[s] = 0.0;
     }
   }
@@ -317,7 +336,7 @@ __device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c
 #endif
 template <typename T>
 struct RowRing {
-  static constexpr int value = sizeof(T) == 4 ? ACR_RING32 : ACR_RING64;
+  static constexpr int value = sizeof(T) == 8 ? ACR_RING64 : ACR_RING32;
 };
 
 // y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi], one block per (job, row
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
           if (!more) {
 #pragma unroll
             for (int sc = 0; sc < RowUnit<T>::NC; ++sc) {
-              u.v[sc][0] = u.v[sc][1] = u.v[sc][2] = u.v[sc][3] = (T)0;
+              u.v[sc][0] = u.v[sc][1] = u.v[sc][2] = u.v[sc][3] = T{};
               u.w[sc] = 0.0;
             }
             return;
@@ -532,19 +551,19 @@ __global__ __launch_bounds__(256) void pack_kernel(const T* src, const int32_t* 
     if (L.fmt == 0) {
       for (int idx = threadIdx.x; idx < ldm * L.n; idx += blockDim.x) {
         const int i = idx % ldm, c = idx / ldm;
-        d[idx] = i < L.m ? s[i + (int64_t)c * L.m] : (T)0;
+        d[idx] = i < L.m ? s[i + (int64_t)c * L.m] : T{};
       }
     } else {
       const int k = rank[l], ldn = (L.n + 3) & ~3;
       for (int idx = threadIdx.x; idx < ldm * k; idx += blockDim.x) {
         const int i = idx % ldm, a = idx / ldm;
-        d[idx] = i < L.m ? s[i + (int64_t)a * L.m] : (T)0;
+        d[idx] = i < L.m ? s[i + (int64_t)a * L.m] : T{};
       }
       const T* sv = s + (int64_t)L.m * L.cap;
       T* dv = d + (int64_t)ldm * k;
       for (int idx = threadIdx.x; idx < ldn * k; idx += blockDim.x) {
         const int c = idx % ldn, a = idx / ldn;
-        dv[idx] = c < L.n ? sv[c + (int64_t)a * L.n] : (T)0;
+        dv[idx] = c < L.n ? sv[c + (int64_t)a * L.n] : T{};
       }
     }
   }
@@ -576,7 +595,23 @@ void launch_mv(const MvArgs<T>& a, hipStream_t s) {
   }
 }
 
+// FP32 -> BF16, round to nearest even (the stored factors are finite).
+__global__ void to_bf16_kernel(const float* src, bf16s* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t u = __float_as_uint(src[i]);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    dst[i].b = (uint16_t)(u >> 16);
+  }
+}
+
+void launch_to_bf16(const float* src, bf16s* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+}
+
 template void launch_mv<double>(const MvArgs<double>&, hipStream_t);
+template void launch_mv<bf16s>(const MvArgs<bf16s>&, hipStream_t);
 template void launch_mv<float>(const MvArgs<float>&, hipStream_t);
 
 }  // namespace acr

@@ -173,6 +173,33 @@ void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
   table_dirty = true;
 }
 
+// ACR_MIXED_BF16: every stored (packed, FP32) factor is replaced by its
+// BF16 rounding, same layout and offsets in elements.
+void Handle::round_factors_bf16(hipStream_t s) {
+  HIPCHK(hipStreamSynchronize(s));
+  const size_t nl = G.lf.size();
+  for (Instance& I : inst) {
+    if (!I.live) continue;
+    if (!I.packed) throw AcrError(ACR_E_DEVICE, "internal: unpacked factor at the end of setup");
+    const int64_t elems = (int64_t)(I.packed_bytes / 4.0);
+    const size_t data = round_up((size_t)elems * 2, 256);
+    const size_t rbytes = round_up(nl * sizeof(int32_t), 256);
+    char* nb = (char*)dmalloc(data + rbytes + nl * sizeof(int64_t));
+    launch_to_bf16((const float*)I.base, (bf16s*)nb, elems, s);
+    HIPCHK(hipMemcpyAsync(nb + data, I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(nb + data + rbytes, I.off, nl * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // the FP32 copy is read until here
+    dfree(I.buf);
+    I.buf = nb;
+    I.base = nb;
+    I.rank = (int32_t*)(nb + data);
+    I.off = (int64_t*)(nb + data + rbytes);
+    I.packed_bytes = (double)elems * 2.0;
+  }
+  HIPCHK(hipGetLastError());
+  table_dirty = true;
+}
+
 void Handle::sync_tables() {
   if (!table_dirty) return;
   if ((int)inst.size() > inst_table_cap) {

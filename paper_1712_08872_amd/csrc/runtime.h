@@ -10,6 +10,7 @@
 
 #include "../../include/acr.h"
 #include "geometry.h"
+#include "bf16.h"
 #include "hprog.h"
 #include "program.h"
 
@@ -46,6 +47,7 @@ void launch_level0(T* const*, const int32_t*, int nplanes, int plane0, const dou
 void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
                       hipStream_t);
 template <typename T> void launch_mv(const MvArgs<T>&, hipStream_t);
+void launch_to_bf16(const float* src, bf16s* dst, int64_t n, hipStream_t s);
 template <typename T>
 void launch_pack(const T* src, const int32_t* rank, const DLeaf* leaves, int nleaf, T* dst, const int64_t* off,
                  hipStream_t);
@@ -123,7 +125,8 @@ struct Handle {
   int nx = 0, ny = 0, nz = 0, B = 0;
   int64_t N = 0;               // unknowns of one problem
   acr_options opt{};
-  bool fp32 = false;
+  bool fp32 = false;  // FP32 factors during setup (ACR_MIXED_FP32 and ACR_MIXED_BF16)
+  bool bf16 = false;  // stored factors rounded to BF16 at the end of setup
   std::vector<Prob> probs;
   // allocator
   std::vector<std::pair<void*, size_t>> owned;
@@ -164,6 +167,7 @@ struct Handle {
   int new_instance(hipStream_t s);
   void release_instance(int id);
   void pack_instances(const std::vector<int>& ids, hipStream_t s);
+  void round_factors_bf16(hipStream_t s);
   void sync_tables();
   // programs
   std::map<std::string, Program> prog;

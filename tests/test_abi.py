@@ -86,3 +86,19 @@ def test_valid_setup_without_device_reports_device_error():
     p = acr.Problem(8, 8, 8, acr.POISSON_HARMONIC, None, 0.0, 0.0, None, 0.0, None)
     st, out = _setup(p, acr.default_options())
     assert st == 7 and out.value is None
+
+
+def test_bf16_factors_need_loose_eps():
+    p = acr.Problem(8, 8, 8, acr.POISSON_HARMONIC, None, 0.0, 0.0, None, 0.0, None)
+    o = acr.default_options()
+    o.precision = acr.MIXED_BF16
+    o.eps = 1e-4
+    st, out = _setup(p, o)
+    assert st == 1 and out.value is None
+    assert b"BF16" in acr.lib().acr_last_error()
+    import torch
+    if torch.cuda.is_available():
+        return
+    o.eps = 1e-2  # accepted by validation; without a device the setup then fails on the device
+    st, out = _setup(p, o)
+    assert st == 7 and out.value is None
