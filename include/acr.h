@@ -152,6 +152,11 @@ typedef struct {
     double bytes_peak;                     /* largest device footprint reached during setup (a
                                               batched handle with several shape groups: the sum
                                               of the groups' peaks, an upper bound) */
+    double bytes_level[ACR_MAX_LEVELS];    /* stored factor bytes per CR level (Dinv and the
+                                              couplings of the level; the top inverse is the
+                                              last level) */
+    double level_seconds[ACR_MAX_LEVELS];  /* setup wall time per CR level (host clock, the
+                                              stream synchronised at level boundaries) */
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("accum_launches", ctypes.c_int32), ("accum_seconds", ctypes.c_double),
                 ("accum_flops", ctypes.c_double), ("dense_launches", ctypes.c_int32),
                 ("dense_seconds", ctypes.c_double), ("dense_flops", ctypes.c_double),
-                ("bytes_peak", ctypes.c_double)]
+                ("bytes_peak", ctypes.c_double), ("bytes_level", ctypes.c_double * MAX_LEVELS),
+                ("level_seconds", ctypes.c_double * MAX_LEVELS)]
 
     def as_dict(self):
         lv = self.levels
@@ -77,7 +78,8 @@ class Stats(ctypes.Structure):
                 "accum_launches": self.accum_launches, "accum_seconds": self.accum_seconds,
                 "accum_flops": self.accum_flops, "dense_launches": self.dense_launches,
                 "dense_seconds": self.dense_seconds, "dense_flops": self.dense_flops,
-                "bytes_peak": self.bytes_peak}
+                "bytes_peak": self.bytes_peak, "bytes_level": list(self.bytes_level[:lv]),
+                "level_seconds": list(self.level_seconds[:lv])}
 
 
 SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",

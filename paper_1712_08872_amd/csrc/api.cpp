@@ -354,6 +354,10 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
     st->dense_seconds += o.dense_seconds;
     st->dense_flops += o.dense_flops;
     st->levels = std::max(st->levels, o.levels);
+    for (int r = 0; r < ACR_MAX_LEVELS; ++r) {
+      st->bytes_level[r] += o.bytes_level[r];
+      st->level_seconds[r] += o.level_seconds[r];
+    }
   }
   return ACR_OK;
 }

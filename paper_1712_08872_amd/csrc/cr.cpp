@@ -163,6 +163,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   st.accum_launches = accum_launches;
   st.dense_launches = dense_launches;
+  for (size_t r = 0; r < level_secs.size() && r < (size_t)ACR_MAX_LEVELS; ++r) st.level_seconds[r] = level_secs[r];
   if (timing) {
     double ms = 0.0, msd = 0.0;
     for (size_t i = 0; i + 1 < ev_used; i += 2) {
@@ -382,8 +383,17 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     return e && e[0] == '1';
   }();
   const auto t_lev0 = std::chrono::steady_clock::now();
+  level_secs.clear();
+  auto t_mark = t_lev0;
+  auto mark_level = [&] {
+    HIPCHK(hipStreamSynchronize(s));
+    const auto now = std::chrono::steady_clock::now();
+    level_secs.push_back(std::chrono::duration<double>(now - t_mark).count());
+    t_mark = now;
+  };
   while (true) {
     cur_level = lev;
+    if (lev > 0) mark_level();
     if (log) {
       HIPCHK(hipStreamSynchronize(s));
       fprintf(stderr, "[acr] level %d: %zu planes, %.2f s, %.2f GB held (peak %.2f GB)\n", lev, P.size(),
@@ -397,6 +407,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
         pr.top_plane = P[0];
         pr.top_inst = pr.plane_inst[P[0]];
       }
+      mark_level();
       break;
     }
     Level L;
@@ -738,6 +749,7 @@ void Handle::compute_stats() {
     HIPCHK(hipMemcpy(rk.data(), inst[id].rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     const double b = instance_bytes(rk);
     total += b;
+    if (r < ACR_MAX_LEVELS) s.bytes_level[r] += b;
     apply_bytes += weight * b;
     ++nf;
     int mx = 0;

@@ -127,6 +127,7 @@ struct Handle {
   acr_options opt{};
   bool fp32 = false;  // FP32 factors during setup (ACR_MIXED_FP32 and ACR_MIXED_BF16)
   bool bf16 = false;  // stored factors rounded to BF16 at the end of setup
+  std::vector<double> level_secs;  // setup wall time per CR level (last build)
   std::vector<Prob> probs;
   // allocator
   std::vector<std::pair<void*, size_t>> owned;

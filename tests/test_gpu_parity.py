@@ -158,3 +158,7 @@ def test_stats_are_consistent(case):
     assert st["levels"] == len(case["H"].levels) + 1
     assert st["bytes_factors"] > 0 and st["bytes_per_apply"] >= st["bytes_factors"]
     assert st["rank_overflow"] == 0
+    # per-level bytes add up to the total; per-level times to at most the setup time
+    assert len(st["bytes_level"]) == st["levels"] and min(st["bytes_level"]) > 0
+    assert abs(sum(st["bytes_level"]) - st["bytes_factors"]) <= 1e-9 * st["bytes_factors"]
+    assert min(st["level_seconds"]) > 0 and sum(st["level_seconds"]) <= st["setup_seconds"]
