@@ -5,7 +5,7 @@ The setup is the FP32 one; its stored factors are then rounded to BF16
   * the factor bytes are exactly half of the FP32 setup's (same ranks: the
     two setups run the same arithmetic);
   * apply and apply_T within 10 eps of the oracle's FP64 H-matrix cyclic
-    reduction at the same eps (the benchmark spec's tolerance), and apply within
+    reduction at the same eps (the apply tolerance of the parity tests), and apply within
     the BF16 rounding of the FP32 apply;
   * the exact-transpose dot test (the same BF16 values serve both maps);
   * the Krylov solution within 1e-8 of a sparse direct solve.
