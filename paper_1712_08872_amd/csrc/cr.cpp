@@ -154,6 +154,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   }
   if (bf16) round_factors_bf16(s);
   build_apply_jobs();
+  tune_apply(s);
   HIPCHK(hipStreamSynchronize(s));
   const int retries = st.retries, overflow = st.rank_overflow, maxr = st.max_rank_all;
   compute_stats();
@@ -663,7 +664,19 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
     ph = transpose ? &ph_applyT : &ph_apply;
   else
     ph = transpose ? &probs[prob].ph_applyT : &probs[prob].ph_apply;
-  auto phase = [&](const PhaseJobs& pj, auto tag) {
+  for (const PhaseJobs& pj : *ph) launch_phase(pj, pj.ri, s);
+  for (int q = 0; q < np; ++q)
+    if (prob < 0 || q == prob) launch_from_horder(z + (int64_t)q * N, out[q], d_perm, B, N, s);
+  HIPCHK(hipGetLastError());
+}
+
+// One apply phase: the coefficient kernel and the row (column) kernel of
+// its jobs.  ri selects the coefficient kernel's schedule (0: one leaf round
+// per lane group, 1: four); -1 takes it from the phase size.  The schedule
+// changes which wavefront handles a leaf, not the arithmetic of any leaf,
+// so results do not depend on it.
+void Handle::launch_phase(const PhaseJobs& pj, int ri, hipStream_t s) {
+  auto run = [&](auto tag) {
     using T = decltype(tag);
     MvArgs<T> a{};
     a.leaves = d_leaves;
@@ -677,16 +690,14 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
     a.nterms = pj.nterms;
     a.trans = pj.trans;
     a.lr_sorted = pj.trans ? d_lr_t : d_lr_n;
-    {
-      // four leaves per lane group when the phase fills the chip anyway
-      const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
-      const int ri = (int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0;
-      a.rounds = ri ? 4 : 1;
-      a.w4 = pj.trans ? w4_t : w4_n;
-      for (int c = 0; c < 6; ++c) {
-        a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
-        a.cw[c] = cw[ri][c];
-      }
+    const int32_t(*cw)[6] = pj.trans ? cw_t : cw_n;
+    // by size: four leaves per lane group when the phase fills the chip anyway
+    const int r = ri >= 0 ? ri : ((int64_t)pj.nterms * cw[1][5] >= 8192 ? 1 : 0);
+    a.rounds = r ? 4 : 1;
+    a.w4 = pj.trans ? w4_t : w4_n;
+    for (int c = 0; c < 6; ++c) {
+      a.cls[c] = pj.trans ? cls_t[c] : cls_n[c];
+      a.cw[c] = cw[r][c];
     }
     a.inst_base = (T* const*)d_inst_base;
     a.inst_rank = d_inst_rank;
@@ -700,16 +711,53 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
     a.nseg = (int)G.leaf_clusters.size();
     launch_mv<T>(a, s);
   };
-  for (const PhaseJobs& pj : *ph) {
-    if (bf16)
-      phase(pj, bf16s{});
-    else if (fp32)
-      phase(pj, float{});
-    else
-      phase(pj, double{});
-  }
-  for (int q = 0; q < np; ++q)
-    if (prob < 0 || q == prob) launch_from_horder(z + (int64_t)q * N, out[q], d_perm, B, N, s);
+  if (bf16)
+    run(bf16s{});
+  else if (fp32)
+    run(float{});
+  else
+    run(double{});
+}
+
+// Schedule autotuning of the apply: every phase of apply and apply_T is
+// timed (HIP events, three launches after a warm-up) with each coefficient
+// kernel schedule on the handle's own factors, and keeps the faster.  The
+// work vectors are cleared first (their values do not affect the time).
+// ACR_AUTOTUNE=0 keeps the size rule.
+void Handle::tune_apply(hipStream_t s) {
+  tuned_phases = 0;
+  if (const char* e = getenv("ACR_AUTOTUNE"); e && e[0] == '0') return;
+  sync_tables();
+  const size_t np = probs.size();
+  HIPCHK(hipMemsetAsync(g, 0, (size_t)N * np * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(w, 0, (size_t)N * np * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(z, 0, (size_t)N * np * sizeof(double), s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (std::vector<PhaseJobs>* phv : {&ph_apply, &ph_applyT})
+    for (PhaseJobs& pj : *phv) {
+      if (pj.nterms == 0) continue;  // no coefficient work: nothing to choose
+      float best = 0.f;
+      int pick = -1;
+      for (int r = 0; r < 2; ++r) {
+        launch_phase(pj, r, s);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3; ++rep) launch_phase(pj, r, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        if (pick < 0 || t < best) {
+          best = t;
+          pick = r;
+        }
+      }
+      pj.ri = pick;
+      ++tuned_phases;
+    }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
   HIPCHK(hipGetLastError());
 }
 

@@ -102,6 +102,8 @@ struct PhaseJobs {           // device job array of one apply phase
   int32_t* terms = nullptr;  // non-empty H-matrix terms (2 * job + term)
   int nterms = 0;
   int trans = 0;
+  int ri = -1;               // coefficient-kernel schedule: 0 one leaf round per lane
+                             // group, 1 four; -1 by the phase size (set by tune_apply)
 };
 
 // One problem of a handle.  All problems of a handle share the plane shape
@@ -223,6 +225,9 @@ struct Handle {
   template <typename T>
   void run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, hipStream_t s);
   void build_apply_jobs();
+  void launch_phase(const PhaseJobs& pj, int ri, hipStream_t s);
+  void tune_apply(hipStream_t s);
+  int tuned_phases = 0;
   // z_p = M_p^{-1} r_p (or M_p^{-T}) for every problem (prob < 0) or one
   void apply(const std::vector<const double*>& r, const std::vector<double*>& z, bool transpose, int prob,
              hipStream_t s);

@@ -55,3 +55,19 @@ def test_peak_and_held_memory_reported():
     assert st["bytes_factors"] <= st["bytes_allocated"] <= st["bytes_peak"]
     assert st["bytes_allocated"] < 4 * st["bytes_factors"] + (64 << 20)
     h.close()
+
+
+def test_apply_schedule_autotuning_changes_no_result(monkeypatch):
+    # the tuner picks the coefficient kernel's schedule per phase by timing;
+    # the schedule moves leaves between wavefronts but not their arithmetic
+    n = 23
+    kap = _kappa(n, 74)
+    f = torch.from_numpy(synth.rhs_uniform(n ** 3, 75)).cuda()
+    monkeypatch.setenv("ACR_AUTOTUNE", "0")
+    h0 = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=kap, eps=1e-5, leaf_size=16, precision=acr.MIXED_FP32)
+    monkeypatch.setenv("ACR_AUTOTUNE", "1")
+    h1 = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=kap, eps=1e-5, leaf_size=16, precision=acr.MIXED_FP32)
+    assert torch.equal(acr.acr_apply(h0, f), acr.acr_apply(h1, f))
+    assert torch.equal(acr.acr_apply_T(h0, f), acr.acr_apply_T(h1, f))
+    h0.close()
+    h1.close()
