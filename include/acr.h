@@ -59,7 +59,11 @@ typedef enum {
     ACR_POISSON_HARMONIC = 0, /* -div(kappa grad u), harmonic face averages (Sec. 6) */
     ACR_CONVDIFF_UPWIND = 1,  /* -div(kappa grad u) + beta.grad u, first-order upwind (Sec. 7) */
     ACR_HELMHOLTZ = 2,        /* -Lap u - (omega/c)^2 u, 7-point (Sec. 8, FD variant) */
-    ACR_STENCIL7_RAW = 3      /* caller-provided 7-point stencil */
+    ACR_STENCIL7_RAW = 3,     /* caller-provided 7-point stencil */
+    ACR_CONVDIFF_RECIRC = 4   /* -div(kappa grad u) + alpha b(x).grad u with the divergence-free
+                                 recirculating flow b of Sec. 7 (eq. codi), wavenumber a:
+                                 beta_amp = alpha, beta_phase = a; first-order upwind per
+                                 direction at the node */
 } acr_kind;
 
 typedef enum {

@@ -36,14 +36,32 @@ def _interior_mask(nx, ny, nz, d):
     return ok.reshape(-1)
 
 
-def stencil7(kind, nx, ny, nz, kappa=None, beta_amp=0.0, beta_phase=0.0, c=None, omega=0.0):
+def recirculating_flow(x, y, z, a):
+    """The recirculating flow b(x) of Sec. 7 (eq. codi) with wavenumber a:
+    every trigonometric argument is a 2 pi times x, 1/8 + y, 1/8 + z or z
+    as the equation prints them.  Returns (b_x, b_y, b_z); the field is
+    divergence-free (the paper's "b_x + b_y + b_z = 0" is read as
+    div b = 0, which the formula satisfies)."""
+    t = 2.0 * np.pi * a
+    X, Y8, Z8, Z = t * x, t * (0.125 + y), t * (0.125 + z), t * z
+    bx = np.sin(X) * np.sin(Y8) + np.sin(Z8) * np.sin(X)
+    by = np.cos(X) * np.cos(Y8) + np.cos(Y8) * np.cos(Z)
+    bz = np.cos(X) * np.cos(Z8) + np.sin(Y8) * np.sin(Z)
+    return bx, by, bz
+
+
+def stencil7(kind, nx, ny, nz, kappa=None, beta_amp=0.0, beta_phase=0.0, c=None, omega=0.0, alpha=0.0,
+             vortex=1.0):
     """Return the (7, N) stencil of the requested operator.
 
     kind: ``"poisson"`` (-div(kappa grad u)), ``"convdiff"``
     (-div(kappa grad u) + beta . grad u with beta_d(x) =
     beta_amp (1 + 0.5 sin(2 pi x + beta_phase)) in all three directions,
-    upwinded at the node), ``"helmholtz"`` (-Lap u - omega^2/c^2 u).
-    ``kappa`` and ``c`` live on the (nz+2, ny+2, nx+2) node grid.
+    upwinded at the node), ``"recirc"`` (-div(kappa grad u) +
+    alpha b(x) . grad u with the recirculating flow of wavenumber
+    ``vortex``, each component upwinded at the node), ``"helmholtz"``
+    (-Lap u - omega^2/c^2 u).  ``kappa`` and ``c`` live on the
+    (nz+2, ny+2, nx+2) node grid.
     """
     N = nx * ny * nz
     h = (1.0 / (nx + 1), 1.0 / (ny + 1), 1.0 / (nz + 1))
@@ -69,6 +87,16 @@ def stencil7(kind, nx, ny, nz, kappa=None, beta_amp=0.0, beta_phase=0.0, c=None,
         bp, bm = np.maximum(b, 0.0), np.minimum(b, 0.0)
         for axis, (dm, dp) in enumerate([(1, 2), (3, 4), (5, 6)]):
             # beta+ (u_p - u_{p-e})/h + beta- (u_{p+e} - u_p)/h
+            S[0] += (bp - bm) / h[axis]
+            S[dm] += np.where(_interior_mask(nx, ny, nz, dm), -bp / h[axis], 0.0)
+            S[dp] += np.where(_interior_mask(nx, ny, nz, dp), bm / h[axis], 0.0)
+    elif kind == "recirc":
+        zz, yy, xx = np.meshgrid(np.arange(1, nz + 1) * h[2], np.arange(1, ny + 1) * h[1],
+                                 np.arange(1, nx + 1) * h[0], indexing="ij")
+        comps = recirculating_flow(xx, yy, zz, vortex)
+        for axis, (dm, dp) in enumerate([(1, 2), (3, 4), (5, 6)]):
+            b = alpha * comps[axis].reshape(-1)
+            bp, bm = np.maximum(b, 0.0), np.minimum(b, 0.0)
             S[0] += (bp - bm) / h[axis]
             S[dm] += np.where(_interior_mask(nx, ny, nz, dm), -bp / h[axis], 0.0)
             S[dp] += np.where(_interior_mask(nx, ny, nz, dp), bm / h[axis], 0.0)

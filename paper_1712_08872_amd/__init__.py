@@ -17,7 +17,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacr.so")
 
-POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW = 0, 1, 2, 3
+POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW, CONVDIFF_RECIRC = 0, 1, 2, 3, 4
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 CG, FCG, GMRES = 0, 1, 2
 MAX_LEVELS = 32

@@ -63,11 +63,12 @@ acr_status check_problem(const acr_problem* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(ACR_E_INVALID, "grid sizes must be >= 1");
   if ((int64_t)p->nx * p->ny > (1 << 26) || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34))
     return fail(ACR_E_INVALID, "grid too large");
-  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_STENCIL7_RAW) return fail(ACR_E_INVALID, "unknown problem kind");
+  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_CONVDIFF_RECIRC) return fail(ACR_E_INVALID, "unknown problem kind");
   if (p->kind == ACR_STENCIL7_RAW && !p->stencil7) return fail(ACR_E_INVALID, "RAW problem needs stencil7");
   if (p->kind == ACR_HELMHOLTZ && (!p->c || !std::isfinite(p->omega)))
     return fail(ACR_E_INVALID, "Helmholtz problem needs c and a finite omega");
-  if (p->kind == ACR_CONVDIFF_UPWIND && (!std::isfinite(p->beta_amp) || !std::isfinite(p->beta_phase)))
+  if ((p->kind == ACR_CONVDIFF_UPWIND || p->kind == ACR_CONVDIFF_RECIRC) &&
+      (!std::isfinite(p->beta_amp) || !std::isfinite(p->beta_phase)))
     return fail(ACR_E_INVALID, "convection parameters must be finite");
   return ACR_OK;
 }

@@ -76,7 +76,8 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
         launch_check(P.kappa, M, 1, d_flags + FL_NONFINITE, s);
       }
       if (P.kind == ACR_HELMHOLTZ) launch_check(p->c, M, 1, d_flags + FL_NONFINITE, s);
-      launch_assemble(P.kind == ACR_CONVDIFF_UPWIND ? 1 : (P.kind == ACR_HELMHOLTZ ? 2 : 0), nx, ny, nz, P.kappa,
+      launch_assemble(P.kind == ACR_CONVDIFF_UPWIND ? 1 : P.kind == ACR_HELMHOLTZ ? 2 : P.kind == ACR_CONVDIFF_RECIRC ? 3 : 0,
+                      nx, ny, nz, P.kappa,
                       P.beta_amp, P.beta_phase, p->c, P.omega, P.S, s);
       launch_check(P.S, 7 * N, 0, d_flags + FL_NONFINITE, s);
     }

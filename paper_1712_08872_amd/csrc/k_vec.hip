@@ -44,6 +44,22 @@ __global__ void assemble_kernel(int kind, int nx, int ny, int nz, const double* 
     } else if (kind == 2) {
       const double cc = c[q];
       diag -= omega * omega / (cc * cc);
+    } else if (kind == 3) {  // alpha b(x).grad u, b the recirculating flow of wavenumber a = beta_phase
+      const double w2 = 2.0 * M_PI * beta_phase;
+      const double x = (i + 1) * hx, y = (j + 1) * hy, z = (k + 1) * hz;
+      const double sx0 = sin(w2 * x), cx0 = cos(w2 * x);
+      const double sy8 = sin(w2 * (0.125 + y)), cy8 = cos(w2 * (0.125 + y));
+      const double sz8 = sin(w2 * (0.125 + z)), cz8 = cos(w2 * (0.125 + z));
+      const double sz0 = sin(w2 * z), cz0 = cos(w2 * z);
+      const double bv[3] = {beta_amp * (sx0 * sy8 + sz8 * sx0), beta_amp * (cx0 * cy8 + cy8 * cz0),
+                            beta_amp * (cx0 * cz8 + sy8 * sz0)};
+      const double hh[3] = {hx, hy, hz};
+      for (int a = 0; a < 3; ++a) {
+        const double bp = bv[a] > 0.0 ? bv[a] : 0.0, bm = bv[a] < 0.0 ? bv[a] : 0.0;
+        diag += (bp - bm) / hh[a];
+        if (in[2 * a]) off[2 * a] += -bp / hh[a];
+        if (in[2 * a + 1]) off[2 * a + 1] += bm / hh[a];
+      }
     }
     S[p] = diag;
     for (int d = 0; d < 6; ++d) S[(int64_t)(d + 1) * N + p] = off[d];

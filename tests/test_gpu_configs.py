@@ -221,3 +221,25 @@ def test_c4_helmholtz127_gmres():
     assert _oracle_relres(S, n, x.cpu().numpy(), inp["f"]) <= 1e-8
     h.close()
     torch.cuda.empty_cache()
+
+
+@full_only
+def test_f1_recirc127_gmres():
+    """The recirculating-flow convection-diffusion of Sec. 7 (eq. codi) at
+    127^3, alpha = 8, wavenumber 1, kappa = 1, mixed precision, eps 1e-4:
+    GMRES(30) to 1e-8 with the residual recomputed by the oracle's
+    operator, and the transpose identity."""
+    n, alpha, a = 127, 8.0, 1.0
+    f = synth.rhs_uniform(n ** 3, 31)
+    S = assembly.stencil7("recirc", n, n, n, alpha=alpha, vortex=a)
+    h = acr.acr_setup(n, n, n, acr.CONVDIFF_RECIRC, beta_amp=alpha, beta_phase=a, eps=1e-4,
+                      precision=acr.MIXED_FP32)
+    np.testing.assert_allclose(acr.acr_get_stencil(h).cpu().numpy().reshape(7, -1), S, rtol=1e-13,
+                               atol=1e-13 * np.abs(S).max())
+    x, info = acr.krylov_solve(h, _dev(f), method=acr.GMRES, restart=30, rtol=1e-8, maxit=300)
+    print(f"  recirc 127^3: GMRES {info['iters']} iterations, setup {acr.acr_stats(h)['setup_seconds']:.1f} s")
+    assert info["status"] == 0, info
+    assert _oracle_relres(S, n, x.cpu().numpy(), f) <= 1e-8
+    assert _transpose_identity(h, n ** 3, 7) <= 1e-10
+    h.close()
+    torch.cuda.empty_cache()

@@ -42,6 +42,8 @@ CASES = {
     # eps = 1e-4 selects the narrow (38-column) accumulation rounds
     "poisson15_e4": ("poisson", 15, 15, 15, 1e-4, 2.0, 32),
     "convdiff_ragged_e4": ("convdiff", 14, 11, 9, 1e-4, 2.0, 16),
+    # the recirculating flow of Sec. 7 (eq. codi), alpha = 8, one vortex wavelength
+    "recirc_ragged": ("recirc", 15, 12, 10, 1e-5, 2.0, 16),
 }
 
 
@@ -54,6 +56,9 @@ def _inputs(kind, nx, ny, nz, seed=1):
     elif kind == "convdiff":
         S = assembly.stencil7(kind, nx, ny, nz, kappa=kap, beta_amp=60.0, beta_phase=0.9)
         kw = dict(kind=acr.CONVDIFF_UPWIND, kappa=_dev(kap), beta_amp=60.0, beta_phase=0.9)
+    elif kind == "recirc":
+        S = assembly.stencil7(kind, nx, ny, nz, kappa=kap, alpha=8.0, vortex=1.0)
+        kw = dict(kind=acr.CONVDIFF_RECIRC, kappa=_dev(kap), beta_amp=8.0, beta_phase=1.0)
     else:
         c = synth.helmholtz_velocity(nx, seed) if nx == ny == nz else np.ones((nz + 2, ny + 2, nx + 2))
         om = synth.helmholtz_omega(c, nx, ppw=6.0)

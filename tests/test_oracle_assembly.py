@@ -1,5 +1,6 @@
 """Pins of the oracle's 7-point operators (Sec. 6-8 problem statements)."""
 import numpy as np
+import pytest
 import scipy.fft as sfft
 import scipy.sparse.linalg as spla
 
@@ -116,3 +117,46 @@ def test_plane_blocks_reassemble():
             np.testing.assert_array_equal(np.diag(Av[k]), A[k * B:(k + 1) * B, (k - 1) * B:k * B])
         if k < nz - 1:
             np.testing.assert_array_equal(np.diag(Cv[k]), A[k * B:(k + 1) * B, (k + 1) * B:(k + 2) * B])
+
+
+def test_recirculating_flow_hand_values():
+    """b of Sec. 7 (eq. codi) at two points worked by hand, a = 1: at the
+    origin sin(2 pi x) = 0 and the 1/8 shifts give pi/4; at x = 1/4,
+    sin(2 pi x) = 1 and cos(2 pi x) = 0."""
+    r2 = np.sqrt(2.0)
+    np.testing.assert_allclose(assembly.recirculating_flow(0.0, 0.0, 0.0, 1.0), (0.0, r2, r2 / 2), atol=1e-15)
+    np.testing.assert_allclose(assembly.recirculating_flow(0.25, 0.0, 0.0, 1.0), (r2, r2 / 2, 0.0), atol=1e-15)
+
+
+@pytest.mark.parametrize("a", [1.0, 2.0, 3.0])
+def test_recirculating_flow_divergence_free(a):
+    """div b = 0 (central differences of the field at random points)."""
+    rng = np.random.default_rng(int(a))
+    P = rng.uniform(0, 1, (200, 3))
+    d = 1e-5
+    div = np.zeros(len(P))
+    for axis in range(3):
+        e = np.zeros(3)
+        e[axis] = d
+        fp = assembly.recirculating_flow(*(P + e).T, a)[axis]
+        fm = assembly.recirculating_flow(*(P - e).T, a)[axis]
+        div += (fp - fm) / (2 * d)
+    assert np.max(np.abs(div)) <= 1e-6 * 2 * np.pi * a
+
+
+def test_recirc_upwind_consistency():
+    """kappa = 1, u linear: the upwind differences are exact and the
+    diffusion vanishes, so (A u)_p = alpha b(x_p) . grad u at nodes whose
+    six neighbours are interior; the off-diagonals are <= 0 (upwinding)."""
+    nx, ny, nz, alpha, a = 9, 7, 6, 8.0, 1.0
+    S = assembly.stencil7("recirc", nx, ny, nz, alpha=alpha, vortex=a)
+    h = (1.0 / (nx + 1), 1.0 / (ny + 1), 1.0 / (nz + 1))
+    zz, yy, xx = np.meshgrid(np.arange(1, nz + 1) * h[2], np.arange(1, ny + 1) * h[1],
+                             np.arange(1, nx + 1) * h[0], indexing="ij")
+    g = np.array([1.0, -2.0, 0.5])
+    u = (g[0] * xx + g[1] * yy + g[2] * zz).reshape(-1)
+    Au = assembly.apply_stencil(S, u, nx, ny, nz).reshape(nz, ny, nx)
+    bx, by, bz = assembly.recirculating_flow(xx, yy, zz, a)
+    want = alpha * (g[0] * bx + g[1] * by + g[2] * bz)
+    np.testing.assert_allclose(Au[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1], rtol=1e-10, atol=1e-10)
+    assert np.all(S[1:] <= 0)
