@@ -12,8 +12,10 @@ C2  127^3 Poisson, 6-decade sub-cube kappa, eps 1e-4, mixed precision: the
 C5  63^3 adjoint gradient (FP32 factors, FP64 Krylov): central differences
     in seeded directions.
 At full size the convection-diffusion (C3), its 48-problem batch, the
-Helmholtz problem (C4) and the 20-direction gradient check take minutes of
-GPU time each; they run with ACR_FULL_SIZE=1.
+Helmholtz problem (C4), the 20-direction gradient check, the paper's
+recirculating-flow convection-diffusion (Sec. 7, eq. codi: 127^3 and the
+alpha / vortex sweeps at 63^3) and the admissibility / leaf-size sweep take
+minutes of GPU time; they run with ACR_FULL_SIZE=1.
 """
 import json
 import os
@@ -259,6 +261,28 @@ def test_f1_recirc63_alpha_and_vortex_sweep(alpha, a):
                       precision=acr.MIXED_FP32)
     x, info = acr.krylov_solve(h, _dev(f), method=acr.GMRES, restart=30, rtol=1e-8, maxit=300)
     print(f"  recirc 63^3 alpha={alpha} a={a}: GMRES {info['iters']} iterations")
+    assert info["status"] == 0, info
+    assert _oracle_relres(S, n, x.cpu().numpy(), f) <= 1e-8
+    h.close()
+
+
+@full_only
+@pytest.mark.parametrize("eta,leaf", [(1.0, 32), (2.0, 32), (4.0, 32), (8.0, 32), (2.0, 16), (2.0, 64)])
+def test_eta_leaf_sweep63(eta, leaf):
+    """Storage and tuning variants (admissibility eta, leaf size n_min; the
+    memory-versus-eta study of Sec. 4.2): 63^3 sub-cube Poisson, eps 1e-4,
+    mixed; CG to 1e-8 with the oracle residual, and the reported factor
+    memory and ranks for the record."""
+    n = 63
+    kap = synth.kappa_subcubes(n, 11)
+    f = synth.rhs_uniform(n ** 3, 12)
+    S = assembly.stencil7("poisson", n, n, n, kappa=kap)
+    h = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=_dev(kap), eps=1e-4, eta=eta, leaf_size=leaf,
+                      precision=acr.MIXED_FP32)
+    st = acr.acr_stats(h)
+    x, info = acr.krylov_solve(h, _dev(f), method=acr.CG, rtol=1e-8, maxit=300)
+    print(f"  eta={eta} leaf={leaf}: factors {st['bytes_factors'] / 1e9:.3f} GB, max rank {st['max_rank_all']}, "
+          f"setup {st['setup_seconds']:.2f} s, CG {info['iters']} iterations")
     assert info["status"] == 0, info
     assert _oracle_relres(S, n, x.cpu().numpy(), f) <= 1e-8
     h.close()
