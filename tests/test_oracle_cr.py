@@ -14,13 +14,15 @@ def _problem(kind, nx, ny, nz, seed=1):
     elif kind == "helmholtz":
         c = np.ones((nz + 2, ny + 2, nx + 2))
         S = assembly.stencil7(kind, nx, ny, nz, c=c, omega=9.37)
+    elif kind == "recirc":
+        S = assembly.stencil7(kind, nx, ny, nz, kappa=kap, alpha=8.0, vortex=2.0)
     else:
         S = assembly.stencil7(kind, nx, ny, nz, kappa=kap)
     return S, assembly.to_sparse(S, nx, ny, nz).toarray()
 
 
 @pytest.mark.parametrize("dims", [(3, 3, 3), (7, 7, 7), (4, 3, 2), (3, 5, 4), (5, 2, 5), (2, 3, 6), (6, 4, 7)])
-@pytest.mark.parametrize("kind", ["poisson", "convdiff", "helmholtz"])
+@pytest.mark.parametrize("kind", ["poisson", "convdiff", "helmholtz", "recirc"])
 def test_dense_cr_is_exact_solve(dims, kind):
     nx, ny, nz = dims
     S, A = _problem(kind, nx, ny, nz)
