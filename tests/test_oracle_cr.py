@@ -84,10 +84,10 @@ def test_dense_cr_constant_kappa_mode_recurrence():
     np.testing.assert_allclose(np.diag(Q2.T @ Dinv @ Q2), 1.0 / d, rtol=1e-10)
 
 
-@pytest.mark.parametrize("dims", [(15, 15, 15), (13, 9, 6)])
-def test_hacr_eps_to_zero_matches_exact_cr(dims):
+@pytest.mark.parametrize("dims,kind", [((15, 15, 15), "poisson"), ((13, 9, 6), "poisson"), ((13, 9, 6), "recirc")])
+def test_hacr_eps_to_zero_matches_exact_cr(dims, kind):
     nx, ny, nz = dims
-    S, A = _problem("poisson", nx, ny, nz, seed=3)
+    S, A = _problem(kind, nx, ny, nz, seed=3)
     cr = dense_cr.DenseCR(*assembly.plane_blocks(S, nx, ny, nz))
     H = hacr.HACR(S, nx, ny, nz, eps=1e-13, eta=2.0, leaf=16)
     b = synth.rhs_uniform(A.shape[0], 5)
