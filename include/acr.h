@@ -96,8 +96,15 @@ typedef struct {
 typedef void* (*acr_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*acr_free_fn)(void* ptr, void* ctx);
 
+/* Smallest accepted eps.  The truncation T_eps (Sec. 3.1.5, Sec. 4.3) keeps
+ * the singular values sigma_i > eps sigma_1 of a block; it finds them from
+ * FP64 Gram matrices of the factors, whose eigenvalues resolve singular
+ * values down to about 1e-8 sigma_1, so a smaller eps is rejected with
+ * ACR_E_INVALID instead of being silently met only to about 1e-8. */
+#define ACR_EPS_MIN 1e-7
+
 typedef struct {
-    double eps;                /* block-wise relative truncation accuracy, > 0 */
+    double eps;                /* block-wise relative truncation accuracy, in [ACR_EPS_MIN, 1) */
     double eta;                /* admissibility parameter, > 0 */
     int32_t leaf_size;         /* n_min: cluster leaves have <= leaf_size points (8..64) */
     int32_t precision;         /* acr_precision */

@@ -137,9 +137,28 @@ def _ptr(t):
     if t is None:
         return None
     import torch
-    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
-        "expected a contiguous float64 CUDA tensor"
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, n, name):
+    """Refuse a tensor whose length differs from what the library will
+    read or write through its pointer (a wrong size would be an
+    out-of-bounds device access, which the C ABI cannot detect)."""
+    if t is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+
+
+def _grid(nx, ny, nz):
+    return (nx + 2) * (ny + 2) * (nz + 2)
+
+
+def _check_problem(nx, ny, nz, kappa, c, stencil7):
+    if min(nx, ny, nz) >= 1:
+        _need(kappa, _grid(nx, ny, nz), "kappa")
+        _need(c, _grid(nx, ny, nz), "c")
+        _need(stencil7, 7 * nx * ny * nz, "stencil7")
 
 
 def _stream(stream=None):
@@ -191,6 +210,7 @@ def acr_setup(nx, ny, nz, kind=POISSON_HARMONIC, kappa=None, beta_amp=0.0, beta_
               stencil7=None, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64, max_rank=0, dense_work=0,
               stream=None):
     """``acr_setup``: returns a :class:`Handle`.  Tensors are float64 CUDA."""
+    _check_problem(nx, ny, nz, kappa, c, stencil7)
     p = Problem(nx, ny, nz, kind, _ptr(kappa), beta_amp, beta_phase, _ptr(c), omega, _ptr(stencil7))
     o = default_options(eps=eps, eta=eta, leaf_size=leaf_size, precision=precision, max_rank=max_rank,
                         dense_work=dense_work)
@@ -206,6 +226,8 @@ def acr_setup_batched(problems, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64,
     omega, stencil7).  Returns one :class:`Handle`."""
     arr = (Problem * len(problems))()
     keep = []
+    for d in problems:
+        _check_problem(d["nx"], d["ny"], d["nz"], d.get("kappa"), d.get("c"), d.get("stencil7"))
     for i, d in enumerate(problems):
         arr[i] = Problem(d["nx"], d["ny"], d["nz"], d.get("kind", POISSON_HARMONIC), _ptr(d.get("kappa")),
                          d.get("beta_amp", 0.0), d.get("beta_phase", 0.0), _ptr(d.get("c")), d.get("omega", 0.0),
@@ -218,10 +240,17 @@ def acr_setup_batched(problems, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64,
     return Handle(out, None, keep)
 
 
+def _nrhs(h, r, z):
+    if r.numel() == 0 or r.numel() % h.total:
+        raise ValueError(f"r has {r.numel()} elements, not a positive multiple of the handle's {h.total} unknowns")
+    _need(z, r.numel(), "z")
+    return r.numel() // h.total
+
+
 def acr_apply(h, r, z=None, stream=None):
     import torch
     z = torch.empty_like(r) if z is None else z
-    nrhs = r.numel() // h.total
+    nrhs = _nrhs(h, r, z)
     _check(lib().acr_apply(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
     return z
 
@@ -229,7 +258,7 @@ def acr_apply(h, r, z=None, stream=None):
 def acr_apply_T(h, r, z=None, stream=None):
     import torch
     z = torch.empty_like(r) if z is None else z
-    nrhs = r.numel() // h.total
+    nrhs = _nrhs(h, r, z)
     _check(lib().acr_apply_T(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)))
     return z
 
@@ -237,6 +266,8 @@ def acr_apply_T(h, r, z=None, stream=None):
 def acr_matvec(h, x, transpose=False, y=None, stream=None):
     import torch
     y = torch.empty_like(x) if y is None else y
+    _need(x, h.total, "x")
+    _need(y, h.total, "y")
     _check(lib().acr_matvec(h.ptr, int(transpose), _ptr(x), _ptr(y), _stream(stream)))
     return y
 
@@ -253,6 +284,8 @@ def krylov_solve(h, b, x=None, method=CG, restart=30, transpose=False, rtol=1e-8
     """Returns ``(x, info_dict)``."""
     import torch
     x = torch.zeros_like(b) if x is None else x
+    _need(b, h.total, "b")
+    _need(x, h.total, "x")
     info = SolveInfo()
     st = lib().krylov_solve(h.ptr, method, restart, int(transpose), rtol, maxit, _ptr(b), _ptr(x),
                             ctypes.byref(info), _stream(stream))
@@ -265,7 +298,10 @@ def krylov_solve(h, b, x=None, method=CG, restart=30, transpose=False, rtol=1e-8
 
 def acr_grad_kappa(h, u, lam, out=None, stream=None):
     import torch
+    _need(u, h.total, "u")
+    _need(lam, h.total, "lam")
     out = torch.empty(h.grid_total, dtype=torch.float64, device="cuda") if out is None else out
+    _need(out, h.grid_total, "out")
     _check(lib().acr_grad_kappa(h.ptr, _ptr(u), _ptr(lam), _ptr(out), _stream(stream)))
     return out
 

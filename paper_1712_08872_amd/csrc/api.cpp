@@ -74,7 +74,12 @@ acr_status check_problem(const acr_problem* p) {
 }
 
 acr_status check_options(const acr_options* o) {
-  if (!(o->eps > 0.0 && o->eps < 1.0)) return fail(ACR_E_INVALID, "eps must lie in (0, 1)");
+  // the truncation forms FP64 Gram matrices of the factors, whose
+  // eigenvalues resolve singular values down to about 1e-8 of the largest:
+  // a smaller eps could not be honoured
+  if (!(o->eps >= ACR_EPS_MIN && o->eps < 1.0))
+    return fail(ACR_E_INVALID, "eps must lie in [1e-7, 1): the truncation resolves singular values only down "
+                               "to about 1e-8 of the largest");
   if (!finite_pos(o->eta)) return fail(ACR_E_INVALID, "eta must be positive");
   if (o->leaf_size < 4 || o->leaf_size > 64) return fail(ACR_E_INVALID, "leaf_size must lie in [4, 64]");
   if (o->precision != ACR_FP64 && o->precision != ACR_MIXED_FP32 && o->precision != ACR_MIXED_BF16)

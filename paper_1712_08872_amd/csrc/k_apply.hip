@@ -350,6 +350,9 @@ struct RowRing {
 template <typename T>
 __global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
   constexpr int D = RowRing<T>::value;
+  // the walker preloads D - 1 units before the loop; with D = 1 nothing
+  // would be issued and every contribution dropped
+  static_assert(D >= 2, "the row kernel's ring needs at least two slots");
   __shared__ double red[4][256];
   __shared__ double part[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -51,7 +51,8 @@ def test_problem_validation(field, value):
     assert acr.lib().acr_last_error()
 
 
-@pytest.mark.parametrize("field,value", [("eps", 0.0), ("eps", -1e-3), ("eps", 1.5), ("eta", 0.0),
+@pytest.mark.parametrize("field,value", [("eps", 0.0), ("eps", -1e-3), ("eps", 1.5), ("eps", 9.9e-8),
+                                         ("eps", 1e-10), ("eta", 0.0),
                                          ("eta", float("nan")), ("leaf_size", 2), ("leaf_size", 65),
                                          ("precision", 5), ("max_rank", -1), ("max_rank", 57),
                                          ("dense_work", 65), ("flags", 1)])
@@ -102,3 +103,15 @@ def test_bf16_factors_need_loose_eps():
     o.eps = 1e-2  # accepted by validation; without a device the setup then fails on the device
     st, out = _setup(p, o)
     assert st == 7 and out.value is None
+
+
+def test_eps_floor_is_stated():
+    """eps below the truncation's resolvable floor is refused with a message
+    that says why (the Gram-matrix truncation resolves singular values only
+    down to about 1e-8 of the largest)."""
+    p = acr.Problem(8, 8, 8, acr.POISSON_HARMONIC, None, 0.0, 0.0, None, 0.0, None)
+    o = acr.default_options()
+    o.eps = 5e-8
+    st, out = _setup(p, o)
+    assert st == 1 and out.value is None
+    assert b"1e-7" in acr.lib().acr_last_error()

@@ -1,0 +1,38 @@
+"""The eps -> 0 limit on the GPU: as eps shrinks the preconditioner
+approaches the exact inverse, so one preconditioned CG iteration leaves a
+residual that shrinks with eps (Sec. 4.3: eps governs the accuracy of the
+H-arithmetic), down to the smallest eps the library accepts (1e-7, the
+floor of the Gram-matrix truncation)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import assembly
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_08872_amd as acr  # noqa: E402
+
+
+def test_one_iteration_residual_shrinks_with_eps():
+    n = 15
+    kap = synth.kappa_lognormal(n, 1)
+    f = synth.rhs_uniform(n ** 3, 2)
+    S = assembly.stencil7("poisson", n, n, n, kappa=kap)
+    dk = torch.from_numpy(kap.reshape(-1)).cuda()
+    b = torch.from_numpy(f).cuda()
+    res = {}
+    for eps in (1e-4, 1e-5, 1e-6, 1e-7):
+        h = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=dk, eps=eps, eta=2.0, leaf_size=16)
+        x, info = acr.krylov_solve(h, b, method=acr.CG, rtol=1e-14, maxit=1, raise_on_fail=False)
+        assert info["iters"] == 1
+        r = f - assembly.apply_stencil(S, x.cpu().numpy(), n, n, n)
+        res[eps] = float(np.linalg.norm(r) / np.linalg.norm(f))
+        assert abs(res[eps] - info["relres_true"]) <= 1e-9
+        h.close()
+    print("  one-iteration relative residual by eps: " + ", ".join(f"{e:g}: {r:.2e}" for e, r in res.items()))
+    vals = [res[e] for e in (1e-4, 1e-5, 1e-6, 1e-7)]
+    # each decade of eps buys at least half a decade of residual
+    assert all(b < a / 3 for a, b in zip(vals, vals[1:])), vals
+    assert res[1e-7] <= 1e-5, res

@@ -5,8 +5,7 @@ Tolerances
     formulas, different rounding order);
   * preconditioner application: ||z_gpu - z_oracle|| / ||z_oracle|| <= 10 eps
     (both sides are eps-accurate H-arithmetic with different accumulation
-    orders), and in any case not worse than 10x the oracle's own distance
-    to the exact solve;
+    orders); the distances of both to the exact solve are printed;
   * transpose: <M^-T x, y> = <x, M^-1 y> to 1e-12 (exact by construction);
   * Krylov solution: relative error <= 1e-8 against a sparse direct solve
     when run to a 1e-12 residual.
@@ -106,7 +105,7 @@ def test_apply_matches_oracle(case):
         err_or = np.linalg.norm(z_or - ex) / np.linalg.norm(ex)
         err_gpu = np.linalg.norm(z - ex) / np.linalg.norm(ex)
         print(f"  apply seed {seed}: |gpu-oracle| {err:.2e}  oracle-exact {err_or:.2e}  gpu-exact {err_gpu:.2e}")
-        assert err <= 10 * eps or err_gpu <= 10 * max(eps, err_or), (err, err_or, err_gpu)
+        assert err <= 10 * eps, (err, err_or, err_gpu)
 
 
 def test_apply_T_matches_oracle_and_is_exact_transpose(case):
