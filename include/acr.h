@@ -229,6 +229,40 @@ acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t 
 acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa,
                           void* stream);
 
+/* Plane geometry (Sec. 3.1.2-3.1.4 with the planar bisection of Sec. 4.2;
+ * eq. admis): the cluster tree of an nx x ny plane (a box with at most
+ * o->leaf_size points is a leaf; otherwise its longer side is split, ties
+ * splitting x, into floor(s/2) and the rest, lower coordinates first),
+ * the block tree under the admissibility test dist > 0 and
+ * min(diam t, diam s) <= o->eta dist (bounding boxes in grid units,
+ * Euclidean), and the H-order of the plane's unknowns (depth-first leaf
+ * order).  This is the geometry acr_setup builds for every plane of that
+ * shape with the same options.  Host only: needs no device.
+ *   info   : counts (required);
+ *   perm   : host, nx*ny int32 or NULL: perm[i] = natural in-plane index
+ *            x + nx*y of H-order position i;
+ *   leaves : host, 6*leaves_cap int32 or NULL: per leaf of the block tree,
+ *            in the library's leaf order, (r0, c0, m, n, admissible,
+ *            low_rank): the block's first row and column in H-order, its
+ *            size, 1 if eq. admis holds, 1 if it is stored low rank (an
+ *            admissible leaf is stored dense when its smaller dimension is
+ *            at most o->dense_work, or when it holds an in-plane coupling
+ *            of the 5-point operator, possible only for large eta);
+ *            ACR_E_INVALID if leaves_cap < info->leaves. */
+typedef struct {
+    int32_t clusters;          /* nodes of the cluster tree */
+    int32_t leaf_clusters;
+    int32_t depth;             /* largest cluster depth (root 0) */
+    int32_t block_nodes;       /* nodes of the block tree */
+    int32_t leaves;            /* leaves of the block tree */
+    int32_t admissible;        /* leaves for which eq. admis holds */
+    int32_t dense_leaves;      /* leaves stored dense */
+    int32_t lr_leaves;         /* leaves stored low rank */
+} acr_geometry_info;
+
+acr_status acr_plane_geometry(int32_t nx, int32_t ny, const acr_options* o, acr_geometry_info* info,
+                              int32_t* perm, int32_t* leaves, int32_t leaves_cap);
+
 /* Statistics of a handle (ranks, bytes, flops, timings). */
 acr_status acr_stats(const acr_handle* h, acr_stats_t* st);
 

@@ -82,9 +82,14 @@ class Stats(ctypes.Structure):
                 "level_seconds": list(self.level_seconds[:lv])}
 
 
+class GeometryInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("clusters", "leaf_clusters", "depth", "block_nodes", "leaves",
+                                              "admissible", "dense_leaves", "lr_leaves")]
+
+
 SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",
            "acr_matvec", "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_destroy",
-           "acr_status_string", "acr_last_error", "acr_default_options"]
+           "acr_status_string", "acr_last_error", "acr_default_options", "acr_plane_geometry"]
 
 _lib = None
 
@@ -119,10 +124,11 @@ def lib():
     L.acr_status_string.argtypes = [i32]
     L.acr_status_string.restype = ctypes.c_char_p
     L.acr_last_error.restype = ctypes.c_char_p
+    L.acr_plane_geometry.argtypes = [i32, i32, ctypes.POINTER(Options), ctypes.POINTER(GeometryInfo), vp, vp, i32]
     L.acr_default_options.argtypes = [ctypes.POINTER(Options)]
     L.acr_default_options.restype = None
     for name in ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_apply", "acr_apply_T", "acr_matvec",
-                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats"]:
+                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_plane_geometry"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -310,6 +316,22 @@ def acr_stats(h):
     s = Stats()
     _check(lib().acr_stats(h.ptr, ctypes.byref(s)))
     return s.as_dict()
+
+
+def acr_plane_geometry(nx, ny, eta=2.0, leaf_size=32, dense_work=0, eps=1e-4):
+    """``acr_plane_geometry`` (host only): returns ``(info, perm, leaves)``
+    with ``info`` a dict of counts, ``perm`` the H-order permutation
+    (int32 numpy array of nx*ny) and ``leaves`` an (nleaves, 6) int32 array
+    of (r0, c0, m, n, admissible, low_rank) in the library's leaf order."""
+    import numpy as np
+    o = default_options(eps=eps, eta=eta, leaf_size=leaf_size, dense_work=dense_work)
+    info = GeometryInfo()
+    _check(lib().acr_plane_geometry(nx, ny, ctypes.byref(o), ctypes.byref(info), None, None, 0))
+    perm = np.empty(nx * ny, dtype=np.int32)
+    leaves = np.empty((info.leaves, 6), dtype=np.int32)
+    _check(lib().acr_plane_geometry(nx, ny, ctypes.byref(o), ctypes.byref(info), perm.ctypes.data_as(ctypes.c_void_p),
+                                    leaves.ctypes.data_as(ctypes.c_void_p), info.leaves))
+    return {k: getattr(info, k) for k, _ in GeometryInfo._fields_}, perm, leaves
 
 
 def acr_destroy(h):

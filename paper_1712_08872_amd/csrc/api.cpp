@@ -334,6 +334,44 @@ acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, dou
   });
 }
 
+acr_status acr_plane_geometry(int32_t nx, int32_t ny, const acr_options* o, acr_geometry_info* info,
+                              int32_t* perm, int32_t* leaves, int32_t leaves_cap) {
+  if (!o || !info) return fail(ACR_E_INVALID, "null argument");
+  if (nx < 1 || ny < 1 || (int64_t)nx * ny > (1 << 26)) return fail(ACR_E_INVALID, "plane sizes out of range");
+  acr_status s = check_options(o);
+  if (s != ACR_OK) return s;
+  return guard([&]() {
+    const acr::Geometry G = acr::build_geometry(nx, ny, o->leaf_size, o->eta, o->dense_work);
+    acr_geometry_info g{};
+    g.clusters = (int32_t)G.cl.size();
+    g.leaf_clusters = (int32_t)G.leaf_clusters.size();
+    g.depth = G.max_depth();
+    g.block_nodes = (int32_t)G.bn.size();
+    g.leaves = (int32_t)G.lf.size();
+    for (const acr::Leaf& L : G.lf) {
+      g.admissible += L.adm;
+      (L.fmt == acr::LF_LR ? g.lr_leaves : g.dense_leaves)++;
+    }
+    *info = g;
+    if (leaves && leaves_cap < g.leaves)
+      throw acr::AcrError(ACR_E_INVALID, "leaves_cap is smaller than the number of leaves");
+    if (perm)
+      for (int i = 0; i < nx * ny; ++i) perm[i] = G.perm[i];
+    if (leaves)
+      for (int l = 0; l < g.leaves; ++l) {
+        const acr::Leaf& L = G.lf[l];
+        int32_t* o6 = leaves + 6 * (int64_t)l;
+        o6[0] = L.r0;
+        o6[1] = L.c0;
+        o6[2] = L.m;
+        o6[3] = L.n;
+        o6[4] = L.adm;
+        o6[5] = L.fmt == acr::LF_LR ? 1 : 0;
+      }
+    return ACR_OK;
+  });
+}
+
 acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
   if (!h || !st) return fail(ACR_E_INVALID, "null argument");
   // one group: its statistics; several groups: sums and maxima
