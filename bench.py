@@ -175,12 +175,15 @@ def cpu_baseline():
     """The oracle (numpy/scipy FP64) on the 31^3 workload: setup + PCG to
     1e-8, wall clock on the host.  One BLAS thread: the oracle's many tiny
     factorizations run several times slower with more."""
-    threads = 1
+    import numpy  # noqa: F401  -- load the BLAS before limiting its threads
+    import scipy.linalg  # noqa: F401
+    threads = None
     try:
-        from threadpoolctl import threadpool_limits
-        threadpool_limits(threads)
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threadpool_limits(1)
+        threads = max(d.get("num_threads", 1) for d in threadpool_info()) if threadpool_info() else 1
     except Exception:
-        threads = None
+        pass
     import synth
     from oracle import assembly, hacr, krylov
     inp = synth.config_inputs("poisson31")

@@ -263,6 +263,54 @@ typedef struct {
 acr_status acr_plane_geometry(int32_t nx, int32_t ny, const acr_options* o, acr_geometry_info* info,
                               int32_t* perm, int32_t* leaves, int32_t leaves_cap);
 
+/* ---- Test hook: factors built elsewhere (e.g. by a CPU reference) ----
+ *
+ * The stored factors of the cyclic reduction (Sec. 4.1, with every plane
+ * block an H-matrix as in Sec. 4.2): per level r of the plane lists
+ * P_0 = (0..nz-1), P_{r+1} = planes at the 1-based even positions of P_r,
+ * the inverse Dinv_i of every eliminated plane i (1-based odd positions of
+ * P_r) and the couplings A_p (to the previous plane of P_r) and C_p (to the
+ * next) of every plane p of P_r, as they are before level r updates them;
+ * the last level holds the single remaining plane's inverse only.  A
+ * coupling that is not given is absent (zero).  acr_import_factors loads
+ * such a factorisation instead of computing it, so that acr_apply,
+ * acr_apply_T and krylov_solve run on exactly the given factors.
+ *
+ * Each factor's data is on the HOST, read during the call only (the caller
+ * keeps ownership).  An H-matrix factor lists its leaves in the order of
+ * acr_plane_geometry (same nx, ny and options): a dense leaf as m x n
+ * column-major, a low-rank leaf as U (m x k, column-major) followed by
+ * V (n x k, column-major) with the block U V^T and k = ranks[l]
+ * (0 <= k <= min(m, n); entries of dense leaves are ignored).  Rows and
+ * columns are in H-order.  A diagonal factor (diag = 1, the level-0
+ * z-couplings) holds nx*ny doubles in H-order. */
+typedef enum { ACR_FACTOR_DINV = 0, ACR_FACTOR_A = 1, ACR_FACTOR_C = 2 } acr_factor_role;
+
+typedef struct {
+    int32_t level;             /* cyclic-reduction level r (the top inverse: the last level) */
+    int32_t role;              /* acr_factor_role */
+    int32_t plane;             /* 0-based plane index k */
+    int32_t diag;              /* 1: diagonal coupling (nx*ny doubles), 0: H-matrix */
+    const int32_t* ranks;      /* host, one per leaf (H-matrix factors) */
+    const double* data;        /* host, the leaves in order (or the diagonal) */
+} acr_factor;
+
+typedef struct {
+    int32_t count;
+    const acr_factor* factors; /* host array of count factors */
+} acr_factor_blob;
+
+/* A handle for problem p (its operator is assembled as in acr_setup, for
+ * acr_matvec and krylov_solve) whose preconditioner is the given
+ * factorisation.  o->precision ACR_FP64 stores the factors as given,
+ * ACR_MIXED_FP32 rounds them to FP32 (ACR_MIXED_BF16 is refused); the
+ * geometry follows o->leaf_size, o->eta and o->dense_work.  ACR_E_INVALID
+ * if a factor is out of range or duplicated, a rank is out of range, a
+ * required inverse is missing or an H-matrix factor has no data.  Used by
+ * the tests that pin the apply kernels to a reference factorisation. */
+acr_status acr_import_factors(const acr_problem* p, const acr_options* o, const acr_factor_blob* blob, void* stream,
+                              acr_handle** out);
+
 /* Statistics of a handle (ranks, bytes, flops, timings). */
 acr_status acr_stats(const acr_handle* h, acr_stats_t* st);
 

@@ -30,6 +30,7 @@ class HACR:
 
     def __init__(self, S, nx, ny, nz, eps, eta=2.0, leaf=32):
         self.nx, self.ny, self.nz, self.eps = nx, ny, nz, eps
+        f0 = hm.flops_snapshot()
         self.ct = hm.ClusterTree(nx, ny, leaf)
         self.bt = hm.BlockTree(self.ct, eta)
         perm = self.ct.perm
@@ -68,6 +69,8 @@ class HACR:
                 D[j], A[j], C[j] = newD[j], newA[j], newC[j]
             self.levels.append(lev)
             P = K
+        #: algorithmic flops of the setup by class (counter, see hmatrix.FLOPS)
+        self.setup_flops = {k: v - f0[k] for k, v in hm.flops_snapshot().items()}
 
     # ---- helpers
     def _from_sparse(self, Dp):
@@ -195,6 +198,50 @@ class HACR:
                         out.append((r, role, p, cp[1]))
         out.append((len(self.levels), "Dinv", self.top[0], self.top[1]))
         return out
+
+    def apply_bytes(self, esz=8):
+        """Algorithmic bytes of one :meth:`apply` (counter).
+
+        Every step of the sweeps reads the stored factors it multiplies by
+        (an H-matrix at its stored entries times ``esz`` bytes, a level-0
+        diagonal coupling at 8 bytes per entry), the plane vectors it reads
+        and the plane vector it updates, and writes one plane vector (plane
+        vectors are FP64, ``8 nx ny`` bytes).  Per level, forward: each
+        eliminated plane ``w_i = Dinv_i g_i``; each kept plane
+        ``g_j -= A_j w + C_j w`` (reads g_j, the present couplings and their
+        w, writes g_j).  Top: ``z = Dinv g``.  Backward, each eliminated
+        plane: ``rr = g_i - A_i z - C_i z`` then ``z_i = Dinv_i rr``.
+        """
+        vec = 8 * self.nx * self.ny
+
+        def fb(cp):
+            if isinstance(cp, tuple):
+                kind, val = cp
+                return 8 * val.size if kind == "diag" else esz * val.stats()[0]
+            return esz * cp.stats()[0]
+
+        total = 0
+        for lev in self.levels:
+            P = lev["P"]
+            for i in lev["E"]:
+                total += 2 * vec + fb(lev["Dinv"][i])
+            for m, j in enumerate(lev["K"]):
+                pos = 2 * m + 1
+                total += 2 * vec + vec + fb(lev["A"][j])
+                if pos + 1 < len(P):
+                    total += vec + fb(lev["C"][j])
+        total += 2 * vec + fb(self.top[1])
+        for lev in reversed(self.levels):
+            P = lev["P"]
+            for m, i in enumerate(lev["E"]):
+                pos = 2 * m
+                total += 2 * vec
+                if pos > 0:
+                    total += vec + fb(lev["A"][i])
+                if pos + 1 < len(P):
+                    total += vec + fb(lev["C"][i])
+                total += 2 * vec + fb(lev["Dinv"][i])
+        return total
 
     def stats(self):
         """Stored FP64 entries, per-level max and mean rank."""

@@ -29,6 +29,31 @@ pivoting) inverses of the dense diagonal leaves.
 import numpy as np
 import scipy.linalg as sla
 
+# ------------------------------------------------------------- counters
+# Algorithmic flops of the H-arithmetic by class (counters, not timings):
+#   gemm          2 m n k for every product of an m x k and a k x n matrix;
+#   qr            4 m K^2 - 4 K^3 / 3 for a Householder QR of an m x K
+#                 factor with Q formed;
+#   svd           22 K^3 for the SVD of a K x K core; 14 M n^2 + 8 n^3
+#                 (M >= n) for the thin SVD of an M x n dense block;
+#   rebuild       2 m K k for forming an m x k truncated factor from Q;
+#   leaf_inverse  2 m^3 for the LU factorisation and inverse of an m x m leaf.
+FLOPS = {"gemm": 0, "qr": 0, "svd": 0, "rebuild": 0, "leaf_inverse": 0}
+
+
+def reset_flops():
+    for k in FLOPS:
+        FLOPS[k] = 0
+
+
+def flops_snapshot():
+    return dict(FLOPS)
+
+
+def _svd_flops(m, n):
+    M, q = max(m, n), min(m, n)
+    return 14 * M * q * q + 8 * q ** 3
+
 
 # ---------------------------------------------------------------- trees
 class ClusterTree:
@@ -128,20 +153,26 @@ def truncate(U, V, eps, max_rank=0):
     if K == 0:
         return np.zeros((m, 0)), np.zeros((n, 0))
     if K >= min(m, n):
+        FLOPS["gemm"] += 2 * m * n * K
         return compress_dense(U @ V.T, eps, max_rank)
     Qu, Ru = sla.qr(U, mode="economic", check_finite=False)
     Qv, Rv = sla.qr(V, mode="economic", check_finite=False)
+    FLOPS["qr"] += 4 * (m + n) * K * K - 8 * K ** 3 // 3
     W, s, Zt = sla.svd(Ru @ Rv.T, check_finite=False)
+    FLOPS["gemm"] += 2 * K ** 3
+    FLOPS["svd"] += 22 * K ** 3
     if s.size == 0 or s[0] == 0.0:
         return np.zeros((m, 0)), np.zeros((n, 0))
     k = int(np.count_nonzero(s > eps * s[0]))
     if max_rank:
         k = min(k, max_rank)
+    FLOPS["rebuild"] += 2 * (m + n) * K * k
     return (Qu @ W[:, :k]) * s[:k], Qv @ Zt[:k].T
 
 
 def compress_dense(M, eps, max_rank=0):
     """Best rank-k approximation of a dense block with ``sigma_i > eps sigma_1``."""
+    FLOPS["svd"] += _svd_flops(*M.shape)
     W, s, Zt = sla.svd(M, full_matrices=False, check_finite=False)
     if s.size == 0 or s[0] == 0.0:
         return np.zeros((M.shape[0], 0)), np.zeros((M.shape[1], 0))
@@ -251,9 +282,12 @@ class HM:
     def matvec(self, X, transpose=False):
         """``H X`` (or ``H^T X``) for a dense ``X`` with one column per vector."""
         X = np.asarray(X, dtype=np.float64)
+        ncol = X.shape[1] if X.ndim > 1 else 1
         if self.kind == "D":
+            FLOPS["gemm"] += 2 * self.D.size * ncol
             return (self.D.T if transpose else self.D) @ X
         if self.kind == "L":
+            FLOPS["gemm"] += 2 * (self.U.size + self.V.size) * ncol
             if transpose:
                 return self.V @ (self.U.T @ X)
             return self.U @ (self.V.T @ X)
@@ -311,6 +345,8 @@ def add_piece(C, alpha, P, eps, t0=None, s0=None):
             for c in row:
                 add_piece(c, alpha, P, eps, C.t, C.s)
     elif C.kind == "D":
+        if P[0] == "L":
+            FLOPS["gemm"] += 2 * C.D.size * P[1].shape[1]
         C.D += alpha * (P[1] @ P[2].T if P[0] == "L" else P[1])
     else:
         if P[0] == "L":
@@ -342,12 +378,15 @@ def _product(A, B):
     if B.kind == "L":
         return ("L", A.matvec(B.U), B.V)
     if A.kind == "D" and B.kind == "D":
+        FLOPS["gemm"] += 2 * A.D.shape[0] * A.D.shape[1] * B.D.shape[1]
         return ("D", A.D @ B.D)
     if A.kind == "D":
         return ("D", B.matvec(A.D.T, transpose=True).T)
     if B.kind == "D":
         return ("D", A.matvec(B.D))
-    return ("D", A.to_dense() @ B.to_dense())
+    a, b = A.to_dense(), B.to_dense()
+    FLOPS["gemm"] += 2 * a.shape[0] * a.shape[1] * b.shape[1]
+    return ("D", a @ b)
 
 
 def mul(alpha, A, B, C, eps):
@@ -366,6 +405,7 @@ def inverse(M, eps):
     """H-inverse of a diagonal block ``(t, t)`` by the recursive 2 x 2
     Schur-complement formula; returns a new HM, ``M`` is consumed."""
     if M.kind == "D":
+        FLOPS["leaf_inverse"] += 2 * M.D.shape[0] ** 3
         lu, piv = sla.lu_factor(M.D)
         M.D = sla.lu_solve((lu, piv), np.eye(M.D.shape[0]))
         return M

@@ -82,6 +82,18 @@ class Stats(ctypes.Structure):
                 "level_seconds": list(self.level_seconds[:lv])}
 
 
+class Factor(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("role", ctypes.c_int32), ("plane", ctypes.c_int32),
+                ("diag", ctypes.c_int32), ("ranks", ctypes.c_void_p), ("data", ctypes.c_void_p)]
+
+
+class FactorBlob(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("factors", ctypes.POINTER(Factor))]
+
+
+FACTOR_DINV, FACTOR_A, FACTOR_C = 0, 1, 2
+
+
 class GeometryInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("clusters", "leaf_clusters", "depth", "block_nodes", "leaves",
                                               "admissible", "dense_leaves", "lr_leaves")]
@@ -89,7 +101,8 @@ class GeometryInfo(ctypes.Structure):
 
 SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",
            "acr_matvec", "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_destroy",
-           "acr_status_string", "acr_last_error", "acr_default_options", "acr_plane_geometry"]
+           "acr_status_string", "acr_last_error", "acr_default_options", "acr_plane_geometry",
+           "acr_import_factors"]
 
 _lib = None
 
@@ -124,11 +137,13 @@ def lib():
     L.acr_status_string.argtypes = [i32]
     L.acr_status_string.restype = ctypes.c_char_p
     L.acr_last_error.restype = ctypes.c_char_p
+    L.acr_import_factors.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(FactorBlob),
+                                     vp, ctypes.POINTER(vp)]
     L.acr_plane_geometry.argtypes = [i32, i32, ctypes.POINTER(Options), ctypes.POINTER(GeometryInfo), vp, vp, i32]
     L.acr_default_options.argtypes = [ctypes.POINTER(Options)]
     L.acr_default_options.restype = None
     for name in ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_apply", "acr_apply_T", "acr_matvec",
-                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_plane_geometry"]:
+                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_plane_geometry", "acr_import_factors"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -316,6 +331,35 @@ def acr_stats(h):
     s = Stats()
     _check(lib().acr_stats(h.ptr, ctypes.byref(s)))
     return s.as_dict()
+
+
+def acr_import_factors(nx, ny, nz, factors, kind=POISSON_HARMONIC, kappa=None, beta_amp=0.0, beta_phase=0.0,
+                       c=None, omega=0.0, stencil7=None, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64,
+                       dense_work=0, stream=None):
+    """``acr_import_factors``: a :class:`Handle` whose preconditioner is the
+    given factorisation.  ``factors`` is a list of dicts with keys level,
+    role (FACTOR_DINV / FACTOR_A / FACTOR_C), plane, diag (bool), ranks
+    (int32 numpy array, one per leaf; H-matrix factors) and data (float64
+    numpy array: the leaves in the order of :func:`acr_plane_geometry`, or
+    the diagonal), all on the host."""
+    import numpy as np
+    _check_problem(nx, ny, nz, kappa, c, stencil7)
+    keep = []
+    arr = (Factor * len(factors))()
+    for i, f in enumerate(factors):
+        data = np.ascontiguousarray(f["data"], dtype=np.float64)
+        ranks = None if f.get("diag") else np.ascontiguousarray(f["ranks"], dtype=np.int32)
+        keep.append((data, ranks))
+        arr[i] = Factor(f["level"], f["role"], f["plane"], int(bool(f.get("diag"))),
+                        None if ranks is None else ranks.ctypes.data_as(ctypes.c_void_p),
+                        data.ctypes.data_as(ctypes.c_void_p))
+    blob = FactorBlob(len(factors), arr)
+    p = Problem(nx, ny, nz, kind, _ptr(kappa), beta_amp, beta_phase, _ptr(c), omega, _ptr(stencil7))
+    o = default_options(eps=eps, eta=eta, leaf_size=leaf_size, precision=precision, dense_work=dense_work)
+    out = ctypes.c_void_p()
+    _check(lib().acr_import_factors(ctypes.byref(p), ctypes.byref(o), ctypes.byref(blob), _stream(stream),
+                                    ctypes.byref(out)))
+    return Handle(out, (nx, ny, nz), (kappa, c, stencil7))
 
 
 def acr_plane_geometry(nx, ny, eta=2.0, leaf_size=32, dense_work=0, eps=1e-4):

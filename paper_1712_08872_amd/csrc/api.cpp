@@ -215,6 +215,44 @@ acr_status acr_setup_batched(const acr_problem* ps, int32_t count, const acr_opt
   return setup_many(ps, count, o, stream, out);
 }
 
+acr_status acr_import_factors(const acr_problem* p, const acr_options* o, const acr_factor_blob* blob, void* stream,
+                              acr_handle** out) {
+  if (out) *out = nullptr;
+  if (!p || !o || !blob || !out || (blob->count > 0 && !blob->factors)) return fail(ACR_E_INVALID, "null argument");
+  if (blob->count < 1) return fail(ACR_E_INVALID, "no factors");
+  acr_status s = check_problem(p);
+  if (s != ACR_OK) return s;
+  s = check_options(o);
+  if (s != ACR_OK) return s;
+  s = guard([&]() {
+    acr::check_factor_blob(p, o, blob);
+    return ACR_OK;
+  });
+  if (s != ACR_OK) return s;
+  s = device_check();
+  if (s != ACR_OK) return s;
+  acr_handle* h = nullptr;
+  s = guard([&]() {
+    h = new acr_handle();
+    h->where.emplace_back(0, 0);
+    h->off.push_back(0);
+    h->grid_off.push_back(0);
+    h->total = (int64_t)p->nx * p->ny * p->nz;
+    h->grid_total = (int64_t)(p->nx + 2) * (p->ny + 2) * (p->nz + 2);
+    auto grp = std::make_unique<acr::Handle>();
+    grp->opt = *o;
+    grp->import_factors(p, blob, (hipStream_t)stream);
+    h->groups.push_back(std::move(grp));
+    return ACR_OK;
+  });
+  if (s != ACR_OK) {
+    delete h;
+    return s;
+  }
+  *out = h;
+  return ACR_OK;
+}
+
 acr_status acr_problem_offset(const acr_handle* h, int32_t i, int64_t* off, int64_t* n, int64_t* grid_off,
                               int64_t* grid_n) {
   if (!h) return fail(ACR_E_INVALID, "null handle");

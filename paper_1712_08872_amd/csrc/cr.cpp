@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 
 #include "runtime.h"
 
@@ -37,6 +38,44 @@ static std::vector<int> initial_caps(const acr_options& o, int depth) {
 
 void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   auto t_start = std::chrono::steady_clock::now();
+  prepare(ps, count, s);
+  int32_t hflags[FL_COUNT];
+  std::vector<int> caps = initial_caps(opt, G.max_depth());
+  for (int attempt = 0;; ++attempt) {
+    build_factors(s, caps);
+    HIPCHK(hipMemcpyAsync(hflags, d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflags[FL_SINGULAR]) throw AcrError(ACR_E_SINGULAR, "exactly singular dense leaf in an H-inverse");
+    if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite value during setup");
+    if (hflags[FL_LAYOUT]) throw AcrError(ACR_E_DEVICE, "internal: packed instance used as a target");
+    int cmax = *std::max_element(caps.begin(), caps.end());
+    // a caller-given max_rank is a fixed cap: ranks are clamped to it and
+    // the overflow is reported, not retried
+    if (!hflags[FL_RANK_OVERFLOW] || opt.max_rank > 0 || cmax >= KC_MAX - 8 || attempt >= 3) {
+      st.max_rank_all = hflags[FL_MAXRANK];
+      st.retries = attempt;
+      if (hflags[FL_RANK_OVERFLOW]) st.rank_overflow = 1;
+      break;
+    }
+    // rank capacity exhausted: redo with larger capacities (the pooled
+    // capacity buffers have the old layout)
+    free_factors();
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* b : cap_pool) dfree(b);
+    cap_pool.clear();
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
+    accum_launches = dense_launches = 0;
+    ev_used = 0;
+    ev_tag.clear();
+    for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
+    HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
+  }
+  finish(s, t_start);
+}
+
+// Operators of every problem (assembly and checks), the plane geometry with
+// its segment tables, and the level-0 z-couplings.
+void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
   nx = ps[0].nx;
   ny = ps[0].ny;
   nz = ps[0].nz;
@@ -112,37 +151,11 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     P.zC = dnew<double>(N);
     launch_zcoupling(P.S, N, B, nz, d_perm, P.zA, P.zC, s);
   }
+}
 
-  std::vector<int> caps = initial_caps(opt, G.max_depth());
-  for (int attempt = 0;; ++attempt) {
-    build_factors(s, caps);
-    HIPCHK(hipMemcpyAsync(hflags, d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hflags[FL_SINGULAR]) throw AcrError(ACR_E_SINGULAR, "exactly singular dense leaf in an H-inverse");
-    if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite value during setup");
-    if (hflags[FL_LAYOUT]) throw AcrError(ACR_E_DEVICE, "internal: packed instance used as a target");
-    int cmax = *std::max_element(caps.begin(), caps.end());
-    // a caller-given max_rank is a fixed cap: ranks are clamped to it and
-    // the overflow is reported, not retried
-    if (!hflags[FL_RANK_OVERFLOW] || opt.max_rank > 0 || cmax >= KC_MAX - 8 || attempt >= 3) {
-      st.max_rank_all = hflags[FL_MAXRANK];
-      st.retries = attempt;
-      if (hflags[FL_RANK_OVERFLOW]) st.rank_overflow = 1;
-      break;
-    }
-    // rank capacity exhausted: redo with larger capacities (the pooled
-    // capacity buffers have the old layout)
-    free_factors();
-    HIPCHK(hipStreamSynchronize(s));
-    for (void* b : cap_pool) dfree(b);
-    cap_pool.clear();
-    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
-    accum_launches = dense_launches = 0;
-    ev_used = 0;
-    ev_tag.clear();
-    for (auto& c : caps) c = std::min(KC_MAX - 8, std::max(c + 8, (int)(c * 1.5)));
-    HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
-  }
+// After the factors exist: release the setup's working memory, round to
+// BF16 if asked, build and tune the apply phases, and gather statistics.
+void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start) {
   // working memory of the setup: recycled capacity buffers and the
   // accumulation scratch
   HIPCHK(hipStreamSynchronize(s));
@@ -161,7 +174,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
   compute_stats();
   st.retries = retries;
   st.rank_overflow = overflow;
-  st.max_rank_all = maxr;
+  st.max_rank_all = std::max(st.max_rank_all, maxr);  // the largest rank produced, stored or not
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   st.accum_launches = accum_launches;
   st.dense_launches = dense_launches;
@@ -216,66 +229,71 @@ void Handle::free_factors() {
     if (inst[i].live) release_instance((int)i);
 }
 
+// Device leaf table, coefficient slots and the coefficient kernel's leaf
+// classes, from the leaves' current capacities.
+void Handle::upload_leaf_tables() {
+  std::vector<DLeaf> dl(G.lf.size());
+  for (size_t i = 0; i < G.lf.size(); ++i) {
+    const Leaf& L = G.lf[i];
+    dl[i] = DLeaf{L.m, L.n, L.r0, L.c0, L.fmt, L.cap, L.off};
+  }
+  if (d_leaves) dfree(d_leaves);
+  d_leaves = upload(dl);
+  std::vector<int32_t> lrl;
+  std::vector<int64_t> soff(G.lf.size(), 0);
+  int64_t acc = 0;
+  for (size_t i = 0; i < G.lf.size(); ++i)
+    if (G.lf[i].fmt == LF_LR) {
+      lrl.push_back((int32_t)i);
+      soff[i] = acc;
+      acc += G.lf[i].cap;
+    }
+  sstride = std::max<int64_t>(acc, 1);
+  if (d_lr_leaves) dfree(d_lr_leaves);
+  if (d_soff) dfree(d_soff);
+  d_lr_leaves = upload(lrl);
+  d_soff = upload(soff);
+  // coefficient kernel order: low-rank leaves by the lane-group class of
+  // the factor length it reduces over (n for V^T x, m for U^T x)
+  auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6], int32_t& w4) {
+    // elements per lane of the coefficient kernel: 4 (FP64 factors) or 8 (FP32)
+    const int e = fp32 ? 8 : 4;
+    auto cl = [e](int len) {
+      return len <= 4 * e ? 0 : len <= 8 * e ? 1 : len <= 16 * e ? 2 : len <= 32 * e ? 3 : 4;
+    };
+    std::vector<int32_t> v(lrl);
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+      return cl(use_m ? G.lf[a].m : G.lf[a].n) < cl(use_m ? G.lf[b].m : G.lf[b].n);
+    });
+    int cnt[5] = {0, 0, 0, 0, 0};
+    int cap4 = 1;
+    for (int l : v) {
+      const int c = cl(use_m ? G.lf[l].m : G.lf[l].n);
+      cnt[c]++;
+      if (c == 4) cap4 = std::max(cap4, G.lf[l].cap);
+    }
+    // the longest leaves: one wavefront per 4 columns of a leaf
+    w4 = (cap4 + 3) / 4;
+    cls[0] = 0;
+    cw[0][0] = cw[1][0] = 0;
+    for (int c = 0; c < 5; ++c) {
+      cls[c + 1] = cls[c] + cnt[c];
+      for (int ri = 0; ri < 2; ++ri) {
+        const int per_wave = (ri ? 4 : 1) * (64 >> (c + 2));  // rounds of 64 / G leaves
+        cw[ri][c + 1] = cw[ri][c] + (c < 4 ? (cnt[c] + per_wave - 1) / per_wave : cnt[c] * w4);
+      }
+    }
+    if (dst) dfree(dst);
+    dst = upload(v);
+  };
+  by_class(false, d_lr_n, cls_n, cw_n, w4_n);
+  by_class(true, d_lr_t, cls_t, cw_t, w4_t);
+}
+
 void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
   G.assign_caps(caps);
-  // device leaf table (offsets depend on the capacities)
+  upload_leaf_tables();
   {
-    std::vector<DLeaf> dl(G.lf.size());
-    for (size_t i = 0; i < G.lf.size(); ++i) {
-      const Leaf& L = G.lf[i];
-      dl[i] = DLeaf{L.m, L.n, L.r0, L.c0, L.fmt, L.cap, L.off};
-    }
-    if (d_leaves) dfree(d_leaves);
-    d_leaves = upload(dl);
-    std::vector<int32_t> lrl;
-    std::vector<int64_t> soff(G.lf.size(), 0);
-    int64_t acc = 0;
-    for (size_t i = 0; i < G.lf.size(); ++i)
-      if (G.lf[i].fmt == LF_LR) {
-        lrl.push_back((int32_t)i);
-        soff[i] = acc;
-        acc += G.lf[i].cap;
-      }
-    sstride = std::max<int64_t>(acc, 1);
-    if (d_lr_leaves) dfree(d_lr_leaves);
-    if (d_soff) dfree(d_soff);
-    d_lr_leaves = upload(lrl);
-    d_soff = upload(soff);
-    // coefficient kernel order: low-rank leaves by the lane-group class of
-    // the factor length it reduces over (n for V^T x, m for U^T x)
-    auto by_class = [&](bool use_m, int32_t*& dst, int32_t* cls, int32_t (*cw)[6], int32_t& w4) {
-      // elements per lane of the coefficient kernel: 4 (FP64 factors) or 8 (FP32)
-      const int e = fp32 ? 8 : 4;
-      auto cl = [e](int len) {
-        return len <= 4 * e ? 0 : len <= 8 * e ? 1 : len <= 16 * e ? 2 : len <= 32 * e ? 3 : 4;
-      };
-      std::vector<int32_t> v(lrl);
-      std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
-        return cl(use_m ? G.lf[a].m : G.lf[a].n) < cl(use_m ? G.lf[b].m : G.lf[b].n);
-      });
-      int cnt[5] = {0, 0, 0, 0, 0};
-      int cap4 = 1;
-      for (int l : v) {
-        const int c = cl(use_m ? G.lf[l].m : G.lf[l].n);
-        cnt[c]++;
-        if (c == 4) cap4 = std::max(cap4, G.lf[l].cap);
-      }
-      // the longest leaves: one wavefront per 4 columns of a leaf
-      w4 = (cap4 + 3) / 4;
-      cls[0] = 0;
-      cw[0][0] = cw[1][0] = 0;
-      for (int c = 0; c < 5; ++c) {
-        cls[c + 1] = cls[c] + cnt[c];
-        for (int ri = 0; ri < 2; ++ri) {
-          const int per_wave = (ri ? 4 : 1) * (64 >> (c + 2));  // rounds of 64 / G leaves
-          cw[ri][c + 1] = cw[ri][c] + (c < 4 ? (cnt[c] + per_wave - 1) / per_wave : cnt[c] * w4);
-        }
-      }
-      if (dst) dfree(dst);
-      dst = upload(v);
-    };
-    by_class(false, d_lr_n, cls_n, cw_n, w4_n);
-    by_class(true, d_lr_t, cls_t, cw_t, w4_t);
     // level-0 scatter map: in-plane couplings -> dense leaf entries
     std::vector<int64_t> map(5 * (size_t)B, -1);
     std::vector<int> pos(B);
@@ -631,6 +649,7 @@ void Handle::build_apply_jobs() {
       if (jobs.empty()) continue;
       PhaseJobs pj;
       pj.d = upload(jobs);
+      pj.h = jobs;
       pj.n = (int)jobs.size();
       std::vector<int32_t> terms;
       for (size_t jj = 0; jj < jobs.size(); ++jj)
@@ -781,6 +800,12 @@ double Handle::instance_bytes(const std::vector<int32_t>& rk) const {
   return b;
 }
 
+// Statistics.  bytes_per_apply counts the algorithmic traffic of one
+// acr_apply from its job list: every job reads each term's stored factor
+// (H-matrix at its actual ranks and storage precision, or a diagonal
+// coupling in FP64), each term's input plane vector and the base vector if
+// any, and writes its output plane vector (plane vectors FP64).  So each
+// Dinv below the top counts twice (forward and back substitution).
 void Handle::compute_stats() {
   acr_stats_t s{};
   s.levels = (int)probs[0].levels.size() + 1;
@@ -790,16 +815,17 @@ void Handle::compute_stats() {
   s.dense_leaves = G.ndense;
   s.lr_leaves = G.nlr;
   s.precision = opt.precision;
-  double total = 0.0, apply_bytes = 0.0;
+  double total = 0.0;
   double rank_cnt[ACR_MAX_LEVELS] = {0};
   int nf = 0;
+  std::map<int, double> ibytes;
   std::vector<int32_t> rk(G.lf.size());
-  auto level_of = [&](int r, int id, double weight) {
+  auto level_of = [&](int r, int id) {
     HIPCHK(hipMemcpy(rk.data(), inst[id].rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     const double b = instance_bytes(rk);
+    ibytes[id] = b;
     total += b;
     if (r < ACR_MAX_LEVELS) s.bytes_level[r] += b;
-    apply_bytes += weight * b;
     ++nf;
     int mx = 0;
     double sum = 0;
@@ -819,17 +845,25 @@ void Handle::compute_stats() {
   for (const Prob& P : probs) {
     for (size_t r = 0; r < P.levels.size(); ++r) {
       const Level& L = P.levels[r];
-      for (auto& kv : L.dinv) level_of((int)r, kv.second, 2.0);
+      for (auto& kv : L.dinv) level_of((int)r, kv.second);
       for (int p : L.P)
-        for (const Coupling* c : {&L.A.at(p), &L.C.at(p)}) {
-          if (c->kind == 2) level_of((int)r, c->inst, 1.0);
-          if (c->kind == 1) apply_bytes += (double)B * 8.0;
-        }
+        for (const Coupling* c : {&L.A.at(p), &L.C.at(p)})
+          if (c->kind == 2) level_of((int)r, c->inst);
     }
-    level_of((int)P.levels.size(), P.top_inst, 1.0);
-    // vectors: every job reads its inputs and writes its output plane
-    apply_bytes += 2.0 * (double)N * 8.0 * 2.0 * (double)P.levels.size() + 2.0 * (double)N * 8.0;
+    level_of((int)P.levels.size(), P.top_inst);
   }
+  const double vec = 8.0 * B;
+  double apply_bytes = 0.0;
+  for (const PhaseJobs& pj : ph_apply)
+    for (const MvJob& J : pj.h) {
+      apply_bytes += vec * (1 + (J.base ? 1 : 0));  // output, base
+      for (const MvTerm& t : J.t) {
+        if (t.inst >= 0)
+          apply_bytes += vec + ibytes.at(t.inst);
+        else if (t.dvec)
+          apply_bytes += vec + vec;
+      }
+    }
   for (int r = 0; r < ACR_MAX_LEVELS; ++r)
     if (rank_cnt[r] > 0) s.mean_rank[r] /= rank_cnt[r];
   for (int r = 0; r < ACR_MAX_LEVELS; ++r) s.max_rank_all = std::max(s.max_rank_all, s.max_rank[r]);

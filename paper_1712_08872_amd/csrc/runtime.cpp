@@ -120,6 +120,89 @@ void Handle::release_instance(int id) {
   table_dirty = true;
 }
 
+// Storage order of the leaves in packed instances: by first row, then first
+// column, so that the leaves a row segment of the matrix-vector product
+// reads lie together.
+void Handle::ensure_pack_order() {
+  const size_t nl = G.lf.size();
+  if (pack_order.size() == nl) return;
+  pack_order.resize(nl);
+  for (size_t l = 0; l < nl; ++l) pack_order[l] = (int)l;
+  std::stable_sort(pack_order.begin(), pack_order.end(), [&](int a, int b) {
+    const Leaf &A = G.lf[a], &B = G.lf[b];
+    return A.r0 != B.r0 ? A.r0 < B.r0 : A.c0 < B.c0;
+  });
+}
+
+// A packed instance from host data given leaf by leaf in leaf order: dense
+// leaves m x n column-major, low-rank leaves U (m x k) then V (n x k), both
+// column-major, k = rank[l].  Stored in the packed layout at the handle's
+// factor precision.
+int Handle::new_packed_instance(const std::vector<int32_t>& rank, const double* data, hipStream_t s) {
+  ensure_pack_order();
+  const size_t nl = G.lf.size();
+  const size_t esz = fp32 ? 4 : 8;
+  std::vector<int64_t> off(nl), src(nl);
+  int64_t acc = 0, sacc = 0;
+  for (size_t l = 0; l < nl; ++l) {
+    const Leaf& L = G.lf[l];
+    src[l] = sacc;
+    sacc += L.fmt == LF_DENSE ? (int64_t)L.m * L.n : (int64_t)(L.m + L.n) * rank[l];
+  }
+  for (int l : pack_order) {
+    const Leaf& L = G.lf[l];
+    off[l] = acc;
+    const int64_t ldm = (L.m + 3) & ~3, ldn = (L.n + 3) & ~3;
+    acc += L.fmt == LF_DENSE ? ldm * L.n : (ldm + ldn) * rank[l];
+  }
+  std::vector<double> host((size_t)acc, 0.0);
+  for (size_t l = 0; l < nl; ++l) {
+    const Leaf& L = G.lf[l];
+    const int64_t ldm = (L.m + 3) & ~3, ldn = (L.n + 3) & ~3;
+    const double* d = data + src[l];
+    double* o = host.data() + off[l];
+    const int cols = L.fmt == LF_DENSE ? L.n : rank[l];
+    for (int c = 0; c < cols; ++c)
+      for (int i = 0; i < L.m; ++i) o[i + ldm * c] = d[i + (int64_t)L.m * c];
+    if (L.fmt == LF_LR) {
+      const double* dv = d + (int64_t)L.m * rank[l];
+      double* ov = o + ldm * rank[l];
+      for (int c = 0; c < rank[l]; ++c)
+        for (int i = 0; i < L.n; ++i) ov[i + ldn * c] = dv[i + (int64_t)L.n * c];
+    }
+  }
+  const size_t bytes = round_up((size_t)acc * esz, 256);
+  const size_t rbytes = round_up(nl * sizeof(int32_t), 256);
+  char* nb = (char*)dmalloc(bytes + rbytes + nl * sizeof(int64_t));
+  if (fp32) {
+    std::vector<float> hf(host.begin(), host.end());
+    HIPCHK(hipMemcpy(nb, hf.data(), hf.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(hipMemcpy(nb, host.data(), host.size() * 8, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(nb + bytes, rank.data(), nl * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(nb + bytes + rbytes, off.data(), nl * sizeof(int64_t), hipMemcpyHostToDevice));
+  int id;
+  if (!free_inst.empty()) {
+    id = free_inst.back();
+    free_inst.pop_back();
+  } else {
+    id = (int)inst.size();
+    inst.emplace_back();
+  }
+  Instance& I = inst[id];
+  I.buf = nb;
+  I.base = nb;
+  I.rank = (int32_t*)(nb + bytes);
+  I.off = (int64_t*)(nb + bytes + rbytes);
+  I.live = true;
+  I.packed = true;
+  I.packed_bytes = (double)acc * esz;
+  table_dirty = true;
+  (void)s;
+  return id;
+}
+
 // Pack final instances: exact ranks, leading dimensions padded to 4
 // elements, per-leaf offsets; their capacity buffers return to the pool.
 void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
@@ -133,16 +216,7 @@ void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
     Instance& I = inst[id];
     if (!I.live || I.packed) continue;
     HIPCHK(hipMemcpy(rk.data(), I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
-    // storage order: by first row, then first column, so that the leaves
-    // a row segment of the matrix-vector product reads lie together
-    if (pack_order.size() != nl) {
-      pack_order.resize(nl);
-      for (size_t l = 0; l < nl; ++l) pack_order[l] = (int)l;
-      std::stable_sort(pack_order.begin(), pack_order.end(), [&](int a, int b) {
-        const Leaf &A = G.lf[a], &B = G.lf[b];
-        return A.r0 != B.r0 ? A.r0 < B.r0 : A.c0 < B.c0;
-      });
-    }
+    ensure_pack_order();
     int64_t acc = 0;
     for (int l : pack_order) {
       const Leaf& L = G.lf[l];

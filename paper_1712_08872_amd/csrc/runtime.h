@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -98,6 +99,7 @@ struct Level {
 
 struct PhaseJobs {           // device job array of one apply phase
   MvJob* d = nullptr;
+  std::vector<MvJob> h;      // host copy (algorithmic byte count)
   int n = 0;
   int32_t* terms = nullptr;  // non-empty H-matrix terms (2 * job + term)
   int nterms = 0;
@@ -218,6 +220,15 @@ struct Handle {
 
   ~Handle();
   void setup(const acr_problem* ps, int count, hipStream_t s);
+  // operators, geometry and segment tables, level-0 z-couplings
+  void prepare(const acr_problem* ps, int count, hipStream_t s);
+  // release setup memory, apply jobs and their tuning, statistics
+  void finish(hipStream_t s, std::chrono::steady_clock::time_point t_start);
+  void upload_leaf_tables();
+  // factors given on the host (acr_import_factors) instead of the setup
+  void import_factors(const acr_problem* p, const acr_factor_blob* blob, hipStream_t s);
+  int new_packed_instance(const std::vector<int32_t>& rank, const double* data, hipStream_t s);
+  void ensure_pack_order();
   void build_factors(hipStream_t s, const std::vector<int>& caps);
   void free_factors();
   void run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
@@ -235,6 +246,9 @@ struct Handle {
   void compute_stats();
   double instance_bytes(const std::vector<int32_t>& ranks) const;
 };
+
+// host-side validation of acr_import_factors' blob (throws ACR_E_INVALID)
+void check_factor_blob(const acr_problem* p, const acr_options* o, const acr_factor_blob* blob);
 
 }  // namespace acr
 

@@ -8,6 +8,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 try:  # the oracle's many tiny factorizations run fastest single-threaded
+    import numpy  # noqa: F401  -- the BLAS must be loaded before its threads are limited
+    import scipy.linalg  # noqa: F401
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)
 except Exception:  # pragma: no cover
