@@ -168,6 +168,15 @@ typedef struct {
                                               last level) */
     double level_seconds[ACR_MAX_LEVELS];  /* setup wall time per CR level (host clock, the
                                               stream synchronised at level boundaries) */
+    /* algorithmic setup flops by class (Sec. 6.4's operation count, counted in the kernels
+       from the operand sizes of every operation, with ACR_KERNEL_TIMING=1): [0] piece
+       products and dense sums (GEMM-shaped), [1] Gram matrices of the factors, [2] core
+       factorisations (pivoted Cholesky, core products, Jacobi rotations, triangular
+       solves), [3] the products forming the truncated factors */
+    double setup_flops_class[4];
+    double leaf_inverse_flops;             /* 2 m^3 per m x m dense diagonal leaf inverted
+                                              (LU with partial pivoting and inverse), always
+                                              counted; setup_flops = the classes + this */
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

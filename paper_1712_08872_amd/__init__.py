@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("accum_flops", ctypes.c_double), ("dense_launches", ctypes.c_int32),
                 ("dense_seconds", ctypes.c_double), ("dense_flops", ctypes.c_double),
                 ("bytes_peak", ctypes.c_double), ("bytes_level", ctypes.c_double * MAX_LEVELS),
-                ("level_seconds", ctypes.c_double * MAX_LEVELS)]
+                ("level_seconds", ctypes.c_double * MAX_LEVELS), ("setup_flops_class", ctypes.c_double * 4),
+                ("leaf_inverse_flops", ctypes.c_double)]
 
     def as_dict(self):
         lv = self.levels
@@ -79,7 +80,9 @@ class Stats(ctypes.Structure):
                 "accum_flops": self.accum_flops, "dense_launches": self.dense_launches,
                 "dense_seconds": self.dense_seconds, "dense_flops": self.dense_flops,
                 "bytes_peak": self.bytes_peak, "bytes_level": list(self.bytes_level[:lv]),
-                "level_seconds": list(self.level_seconds[:lv])}
+                "level_seconds": list(self.level_seconds[:lv]),
+                "setup_flops_class": dict(zip(("products", "gram", "core", "rebuild"), self.setup_flops_class)),
+                "leaf_inverse_flops": self.leaf_inverse_flops}
 
 
 class Factor(ctypes.Structure):

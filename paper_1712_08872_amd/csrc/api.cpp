@@ -14,10 +14,10 @@
 #include "runtime.h"
 
 namespace acr {
-acr_status krylov_cg(Handle& h, int prob, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
-                     acr_solve_info* info, hipStream_t s);
-acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int maxit, const double* b, double* x,
-                        acr_solve_info* info, hipStream_t s);
+acr_status krylov_cg(Handle& h, KrylovBuffers* wb, int prob, bool flexible, bool tr, double rtol, int maxit,
+                     const double* b, double* x, acr_solve_info* info, hipStream_t s);
+acr_status krylov_gmres(Handle& h, KrylovBuffers* wb, int prob, int m, bool tr, double rtol, int maxit,
+                        const double* b, double* x, acr_solve_info* info, hipStream_t s);
 }  // namespace acr
 
 namespace {
@@ -156,6 +156,61 @@ void for_groups(acr_handle* h, const double* r, double* z, F&& f) {
   }
 }
 }  // namespace
+
+namespace acr {
+
+acr_status set_last_error(acr_status s, const std::string& msg) { return fail(s, msg); }
+
+int krylov_vectors(int32_t method, int32_t restart) { return method == ACR_GMRES ? 2 * restart + 3 : 5; }
+
+acr_status check_solve_args(const acr_handle* h, int32_t method, int32_t restart, double rtol, int32_t maxit,
+                            const double* b, const double* x, const acr_solve_info* info) {
+  if (!h || !b || !x || !info) return fail(ACR_E_INVALID, "null argument");
+  if (b == x) return fail(ACR_E_INVALID, "x must not alias b");
+  if (method < ACR_CG || method > ACR_GMRES) return fail(ACR_E_INVALID, "unknown method");
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(ACR_E_INVALID, "rtol must lie in (0, 1)");
+  if (maxit < 1) return fail(ACR_E_INVALID, "maxit must be >= 1");
+  if (method == ACR_GMRES && (restart < 1 || restart > 60)) return fail(ACR_E_INVALID, "restart must lie in [1, 60]");
+  return ACR_OK;
+}
+
+// krylov_solve: validation, then every problem solved to its own tolerance;
+// the info reports the largest iteration count and residual and the first
+// failure.  wb = nullptr: the handle's own buffers (allocated at the first
+// solve), else the given fixed buffers.
+acr_status solve_problems(acr_handle* h, int32_t method, int32_t restart, int32_t transpose, double rtol,
+                          int32_t maxit, const double* b, double* x, acr_solve_info* info, void* stream,
+                          KrylovBuffers* wb) {
+  acr_status v = check_solve_args(h, method, restart, rtol, maxit, b, x, info);
+  if (v != ACR_OK) return v;
+  std::memset(info, 0, sizeof(*info));
+  acr_status result = ACR_OK;
+  acr_status st = guard([&]() {
+    for (size_t i = 0; i < h->where.size(); ++i) {
+      Handle& g = *h->groups[h->where[i].first];
+      const int q = h->where[i].second;
+      acr_solve_info one{};
+      acr_status r;
+      if (method == ACR_GMRES)
+        r = krylov_gmres(g, wb, q, restart, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
+                         (hipStream_t)stream);
+      else
+        r = krylov_cg(g, wb, q, method == ACR_FCG, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
+                      (hipStream_t)stream);
+      info->iters = std::max(info->iters, one.iters);
+      info->relres_true = std::max(info->relres_true, one.relres_true);
+      if (one.variant == ACR_FCG || i == 0) info->variant = one.variant;
+      if (r != ACR_OK && result == ACR_OK) result = r;
+    }
+    info->status = result;
+    return ACR_OK;
+  });
+  if (st != ACR_OK) return st;
+  if (result != ACR_OK) return fail(result, std::string("krylov_solve: ") + acr_status_string(result));
+  return ACR_OK;
+}
+
+}  // namespace acr
 
 extern "C" {
 
@@ -318,39 +373,7 @@ acr_status acr_get_stencil(acr_handle* h, double* out, void* stream) {
 
 acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t transpose, double rtol, int32_t maxit,
                         const double* b, double* x, acr_solve_info* info, void* stream) {
-  if (!h || !b || !x || !info) return fail(ACR_E_INVALID, "null argument");
-  if (b == x) return fail(ACR_E_INVALID, "x must not alias b");
-  if (method < ACR_CG || method > ACR_GMRES) return fail(ACR_E_INVALID, "unknown method");
-  if (!(rtol > 0.0 && rtol < 1.0)) return fail(ACR_E_INVALID, "rtol must lie in (0, 1)");
-  if (maxit < 1) return fail(ACR_E_INVALID, "maxit must be >= 1");
-  if (method == ACR_GMRES && (restart < 1 || restart > 60)) return fail(ACR_E_INVALID, "restart must lie in [1, 60]");
-  std::memset(info, 0, sizeof(*info));
-  acr_status result = ACR_OK;
-  acr_status st = guard([&]() {
-    // each problem is solved to its own tolerance; the info reports the
-    // largest iteration count and residual and the first failure
-    for (size_t i = 0; i < h->where.size(); ++i) {
-      acr::Handle& g = *h->groups[h->where[i].first];
-      const int q = h->where[i].second;
-      acr_solve_info one{};
-      acr_status r;
-      if (method == ACR_GMRES)
-        r = acr::krylov_gmres(g, q, restart, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
-                              (hipStream_t)stream);
-      else
-        r = acr::krylov_cg(g, q, method == ACR_FCG, transpose != 0, rtol, maxit, b + h->off[i], x + h->off[i], &one,
-                           (hipStream_t)stream);
-      info->iters = std::max(info->iters, one.iters);
-      info->relres_true = std::max(info->relres_true, one.relres_true);
-      if (one.variant == ACR_FCG || i == 0) info->variant = one.variant;
-      if (r != ACR_OK && result == ACR_OK) result = r;
-    }
-    info->status = result;
-    return ACR_OK;
-  });
-  if (st != ACR_OK) return st;
-  if (result != ACR_OK) return fail(result, std::string("krylov_solve: ") + acr_status_string(result));
-  return ACR_OK;
+  return acr::solve_problems(h, method, restart, transpose, rtol, maxit, b, x, info, stream, nullptr);
 }
 
 acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa, void* stream) {
@@ -435,6 +458,8 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
     st->dense_launches += o.dense_launches;
     st->dense_seconds += o.dense_seconds;
     st->dense_flops += o.dense_flops;
+    for (int c = 0; c < 4; ++c) st->setup_flops_class[c] += o.setup_flops_class[c];
+    st->leaf_inverse_flops += o.leaf_inverse_flops;
     st->levels = std::max(st->levels, o.levels);
     for (int r = 0; r < ACR_MAX_LEVELS; ++r) {
       st->bytes_level[r] += o.bytes_level[r];

@@ -63,7 +63,8 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     for (void* b : cap_pool) dfree(b);
     cap_pool.clear();
-    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * FC_COUNT * sizeof(double), s));
+    leaf_inverse_flops = 0.0;
     accum_launches = dense_launches = 0;
     ev_used = 0;
     ev_tag.clear();
@@ -88,8 +89,8 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   if (const char* e = getenv("ACR_KERNEL_TIMING"); e && e[0] == '1') {
     timing = true;
-    d_flops = dnew<double>(2);
-    HIPCHK(hipMemsetAsync(d_flops, 0, 2 * sizeof(double), s));
+    d_flops = dnew<double>(2 * FC_COUNT);
+    HIPCHK(hipMemsetAsync(d_flops, 0, 2 * FC_COUNT * sizeof(double), s));
   }
   if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
     d_prof = dnew<unsigned long long>(PS_COUNT);
@@ -178,6 +179,7 @@ void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   st.accum_launches = accum_launches;
   st.dense_launches = dense_launches;
+  st.leaf_inverse_flops = leaf_inverse_flops;
   for (size_t r = 0; r < level_secs.size() && r < (size_t)ACR_MAX_LEVELS; ++r) st.level_seconds[r] = level_secs[r];
   if (timing) {
     double ms = 0.0, msd = 0.0;
@@ -202,11 +204,16 @@ void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start
         fclose(f);
       }
     }
-    double fl[2] = {0.0, 0.0};
+    // [kernel][class]: the truncating kernel, then the accumulate-only one
+    double fl[2 * FC_COUNT] = {0.0};
     HIPCHK(hipMemcpy(fl, d_flops, sizeof(fl), hipMemcpyDeviceToHost));
-    st.accum_flops = fl[0];
-    st.dense_flops = fl[1];
-    st.setup_flops = fl[0] + fl[1];
+    st.accum_flops = st.dense_flops = 0.0;
+    for (int c = 0; c < FC_COUNT; ++c) {
+      st.accum_flops += fl[c];
+      st.dense_flops += fl[FC_COUNT + c];
+      st.setup_flops_class[c] = fl[c] + fl[FC_COUNT + c];
+    }
+    st.setup_flops = st.accum_flops + st.dense_flops + leaf_inverse_flops;
   }
   if (d_prof) {
     unsigned long long pc[PS_COUNT];

@@ -85,7 +85,16 @@ struct AccumArgs {
   int32_t mode;                // truncating kernel: 0 every low-rank target, 1 all but the dense
                                // sums, 2 the dense sums only
   unsigned long long* prof;    // optional cycle counters (null = off)
-  double* flops;               // optional algorithmic flop counter (null = off)
+  double* flops;               // optional algorithmic flop counters by FlopClass (null = off)
+};
+
+// classes of the algorithmic flop counters of the accumulation kernels
+enum FlopClass : int32_t {
+  FC_PRODUCT = 0,  // piece products and dense sums (GEMM-shaped)
+  FC_GRAM = 1,     // Gram matrices of the factors
+  FC_CORE = 2,     // pivoted Cholesky, core products, Jacobi rotations, triangular solves
+  FC_REBUILD = 3,  // products forming the truncated factors
+  FC_COUNT = 4
 };
 
 // cycle-counter slots of the accumulation kernel

@@ -122,7 +122,7 @@ struct Lds {
   int permU[KC], permV[KC], posU[KC], posV[KC], order[KC], permC[KC], posC[KC];
   int ival[8];
   double dval[4];
-  double flops;          // algorithmic flops of the current item (thread 0)
+  double flops[FC_COUNT];  // algorithmic flops of the block's items by class (thread 0)
 };
 
 // LDS of the accumulate-only kernel: the staging tiles of the piece
@@ -132,12 +132,12 @@ struct LdsPiece {
   CT S0[KC * LDM];
   CT S1[KC * LDM];
   CT S2[KC * LDM];
-  double flops;
+  double flops[FC_COUNT];
 };
 
-#define FLOP(L_, x_)                        \
+#define FLOP(L_, c_, x_)                    \
   do {                                      \
-    if (threadIdx.x == 0) (L_).flops += (double)(x_); \
+    if (threadIdx.x == 0) (L_).flops[c_] += (double)(x_); \
   } while (0)
 
 // Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
@@ -369,7 +369,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   PROF_ADD(PS_KSUM, K);
   gram(Us, m, K, L.S2, L.S1);
   gram(Vs, n, K, L.S0, L.S1);
-  FLOP(L, (double)(m + n) * K * (K + 1));
+  FLOP(L, FC_GRAM, (double)(m + n) * K * (K + 1));
   long long t1 = clock64();
   PROF_ADD(PS_GRAM, t1 - t0);
   // norm balancing of the column pairs: d_j = sqrt(|v_j| / |u_j|)
@@ -397,7 +397,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   }
   __syncthreads();
   const int rU = L.ival[0], rV = L.ival[1];
-  FLOP(L, (double)K * K * (rU + rV));
+  FLOP(L, FC_CORE, (double)K * K * (rU + rV));
   long long t2 = clock64();
   PROF_ADD(PS_EIG1, t2 - t1);
   if (rU == 0 || rV == 0) return 0;
@@ -412,7 +412,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     L.S1[a * LDM + c] = s;
   }
   __syncthreads();
-  FLOP(L, 2.0 * rU * rV * K);
+  FLOP(L, FC_CORE, 2.0 * rU * rV * K);
   // Rank pre-reduction of the core: Cholesky with symmetric pivoting of
   // H = C^T C, stopped once every remaining diagonal entry is below
   // (0.01 eps)^2 max diag(H).  The dropped part E of C then has
@@ -438,7 +438,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
     }
     __syncthreads();
     const int rp = L.ival[6];
-    FLOP(L, (double)rU * rV * rV + (double)rV * rV * rp);
+    FLOP(L, FC_CORE, (double)rU * rV * rV + (double)rV * rV * rp);
     if (rp > 0 && rp + 3 <= rV) {
       // M^T (rV x r'): row i is column pos_C(i) of the pivot-ordered R_C
       double tmp[PER];
@@ -476,7 +476,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
                              : onesided_jacobi(L.S1, L.S3, rU, rV, &L.ival[4], L.dval);
   PROF_ADD(PS_SWEEPS, sweeps);
   const int jrows = reduced ? rV : rU;
-  FLOP(L, (double)sweeps * (rr / 2) * (rr - 1 + (rr & 1)) * (12.0 * jrows + (reduced ? 0.0 : 6.0 * rV)));
+  FLOP(L, FC_CORE, (double)sweeps * (rr / 2) * (rr - 1 + (rr & 1)) * (12.0 * jrows + (reduced ? 0.0 : 6.0 * rV)));
   // singular values = column norms of the rotated matrix; order, rank
   const double* Rot = reduced ? L.S3 : L.S1;
   if (tid < rr) {
@@ -536,7 +536,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
       }
     }
     __syncthreads();
-    FLOP(L, 2.0 * rU * rV * kk);
+    FLOP(L, FC_CORE, 2.0 * rU * rV * kk);
   }
   const int k = L.ival[2];
   if (k == 0) return 0;
@@ -573,7 +573,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   PROF_ADD(PS_EIG2, t3 - t2);
   rebuild(Us, m, K, k, L.S2, L.S1);
   rebuild(Vs, n, K, k, L.S0, L.S1);
-  FLOP(L, (double)k * (rU * rU + rV * rV) + 2.0 * (m + n) * K * k);
+  FLOP(L, FC_REBUILD, (double)k * (rU * rU + rV * rV) + 2.0 * (m + n) * K * k);
   PROF_ADD(PS_REBUILD, clock64() - t3);
   return k;
 }
@@ -796,7 +796,7 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       for (int a = 0; a < kl; ++a) s += (CT)lr.V[(cA - lam.c0 + cc) + (int64_t)a * lr.ldv] * S0c[a * KC + jj];
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
-    FLOP(L, 2.0 * kl * take * (nq + nc));
+    FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + nc));
   } else {
     for (int idx = tid; idx < nc * take; idx += TPB) {
       const int cc = idx / take, jj = idx - cc * take;
@@ -804,7 +804,7 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       for (int q = 0; q < nq; ++q) s += S1c[q * KC + cc] * S2c[q * KC + jj];
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
-    FLOP(L, 2.0 * nq * nc * take);
+    FLOP(L, FC_PRODUCT, 2.0 * nq * nc * take);
   }
   return true;
 }
@@ -870,7 +870,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       for (int a = 0; a < kl; ++a) s += (CT)lr.U[(rA - lam.r0) + r + (int64_t)a * lr.ldu] * S0c[a * KC + jj];
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
-    FLOP(L, 2.0 * kl * take * (nq + nr));
+    FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + nr));
   } else {
     for (int idx = tid; idx < nr * take; idx += TPB) {
       const int r = idx / take, jj = idx - r * take;
@@ -878,7 +878,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       for (int q = 0; q < nq; ++q) s += S1c[q * KC + r] * S2c[q * KC + jj];
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
-    FLOP(L, 2.0 * nq * nr * take);
+    FLOP(L, FC_PRODUCT, 2.0 * nq * nr * take);
   }
   return true;
 }
@@ -937,7 +937,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           const int nc = imin(KC, cB - c0);
           tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, S0c, S1c,
                      S2c, A.prof);
-          FLOP(L, 2.0 * nq * nc * take);
+          FLOP(L, FC_PRODUCT, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
             T* d = &Vs[(int64_t)(c0 + cc - tc.c0) * KC + K + jj];
@@ -953,7 +953,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, S0c, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
                S1c, A.prof);
-        FLOP(L, 2.0 * kl * take * (nq + (cB - cA)));
+        FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (cB - cA)));
       }
     }
   } else if (P.kind == PK_LRY) {
@@ -998,7 +998,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           __syncthreads();
           nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, S0c, take,
                  Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
-          FLOP(L, 2.0 * (rB - rA) * nqc * take);
+          FLOP(L, FC_PRODUCT, 2.0 * (rB - rA) * nqc * take);
         }
       } else {
         const int kl = rank_of(A, xi, l);
@@ -1008,7 +1008,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, S0c, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
                S1c, A.prof);
-        FLOP(L, 2.0 * kl * take * (nq + (rB - rA)));
+        FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (rB - rA)));
       }
     }
   } else if (P.kind == PK_DD) {
@@ -1037,7 +1037,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       __syncthreads();
       nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, take,
              Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
-      FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * take);
+      FLOP(L, FC_PRODUCT, 2.0 * (P.wr1 - P.wr0) * nqc * take);
     }
   } else {  // PK_COPY of a low-rank leaf
     const int si = inst_of(A, b, P.xrole);
@@ -1139,7 +1139,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
           __syncthreads();
           nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, nc,
                  C + (P.wr0 - tc.r0) + (int64_t)(cc0 - tc.c0) * tc.m, 1, tc.m, P.alpha, S1c, A.prof);
-          FLOP(L, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
+          FLOP(L, FC_PRODUCT, 2.0 * (P.wr1 - P.wr0) * nqc * nc);
         }
       }
       PROF_ADD(PS_DDP, clock64() - tpd);
@@ -1166,7 +1166,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
         const long long to = clock64();
         dense_add_outer(C, tc, Us, Vs, take, L);
         PROF_ADD(PS_OUTER, clock64() - to);
-        FLOP(L, 2.0 * tc.m * tc.n * take);
+        FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * take);
       }
     }
   }
@@ -1188,7 +1188,8 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
   unsigned long long* prof = A.prof;
-  if (tid == 0) L.flops = 0.0;
+  if (tid == 0)
+    for (int c = 0; c < FC_COUNT; ++c) L.flops[c] = 0.0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
     const int t = A.t0 + item % A.nt;
@@ -1326,7 +1327,8 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
     }
     __syncthreads();
   }
-  if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
+  if (tid == 0 && A.flops)
+    for (int c = 0; c < FC_COUNT; ++c) atomicAdd(A.flops + c, L.flops[c]);
 }
 
 // The accumulate-only kernel needs only the staging tiles (FP32 tiles for
@@ -1351,7 +1353,8 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
   const int tid = threadIdx.x;
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-  if (tid == 0) L.flops = 0.0;
+  if (tid == 0)
+    for (int c = 0; c < FC_COUNT; ++c) L.flops[c] = 0.0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
     const int t = A.t0 + item % A.nt;
@@ -1391,12 +1394,13 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
       for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
       D[idx] = (T)v;
     }
-    FLOP(L, 2.0 * tc.m * tc.n * k0);
+    FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * k0);
     __syncthreads();
     dense_pieces(A, b, tg, tc, D, Us, Vs, L);
     PROF_ADD(PS_DACC, clock64() - t_item);
   }
-  if (tid == 0 && A.flops) atomicAdd(A.flops, L.flops);
+  if (tid == 0 && A.flops)
+    for (int c = 0; c < FC_COUNT; ++c) atomicAdd(A.flops + c, L.flops[c]);
 }
 
 // ------------------------------------------------------------ launchers

@@ -22,35 +22,41 @@ namespace {
 
 struct KWork {
   Handle& h;
+  KrylovBuffers& wb;
+  const bool fixed;  // caller-given buffers of fixed size: never allocate
   hipStream_t s;
   int64_t N;
   int prob;
-  KWork(Handle& hh, hipStream_t ss, int p) : h(hh), s(ss), N(hh.N), prob(p) {}
+  KWork(Handle& hh, KrylovBuffers* ext, hipStream_t ss, int p)
+      : h(hh), wb(ext ? *ext : hh.kbuf), fixed(ext != nullptr), s(ss), N(hh.N), prob(p) {}
 
   void ensure(size_t nvec) {
-    if (h.kv_len >= nvec) return;
-    if (h.kv) h.dfree(h.kv);
-    h.kv = h.dnew<double>(nvec * (size_t)N);
-    h.kv_len = nvec;
-    if (!h.part) {
-      h.part = h.dnew<double>(64 * 1024);
-      h.dres = h.dnew<double>(64);
-      h.dots_a = h.dnew<const double*>(8);
-      h.dots_b = h.dnew<const double*>(8);
-      HIPCHK(hipHostMalloc((void**)&h.hres, 64 * sizeof(double), hipHostMallocDefault));
+    if (wb.kv_len >= nvec) return;
+    if (fixed)
+      throw AcrError(ACR_E_INVALID, "the Krylov method needs " + std::to_string(nvec) + " work vectors of " +
+                                        std::to_string(N) + " doubles, more than the fixed workspace holds");
+    if (wb.kv) h.dfree(wb.kv);
+    wb.kv = h.dnew<double>(nvec * (size_t)N);
+    wb.kv_len = nvec;
+    if (!wb.part) {
+      wb.part = h.dnew<double>(KRYLOV_PART);
+      wb.dres = h.dnew<double>(KRYLOV_RES);
+      wb.dots_a = h.dnew<const double*>(8);
+      wb.dots_b = h.dnew<const double*>(8);
+      HIPCHK(hipHostMalloc((void**)&wb.hres, KRYLOV_RES * sizeof(double), hipHostMallocDefault));
     }
   }
-  double* vec(int i) { return h.kv + (size_t)i * N; }
+  double* vec(int i) { return wb.kv + (size_t)i * N; }
 
   // nd dot products (a[d], b[d]) -> host
   void dots(const std::vector<const double*>& a, const std::vector<const double*>& b, double* out) {
     int nd = (int)a.size();
-    HIPCHK(hipMemcpyAsync((void*)h.dots_a, a.data(), nd * sizeof(double*), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync((void*)h.dots_b, b.data(), nd * sizeof(double*), hipMemcpyHostToDevice, s));
-    launch_dots(h.dots_a, h.dots_b, nd, N, h.part, h.dres, s);
-    HIPCHK(hipMemcpyAsync(h.hres, h.dres, nd * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync((void*)wb.dots_a, a.data(), nd * sizeof(double*), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((void*)wb.dots_b, b.data(), nd * sizeof(double*), hipMemcpyHostToDevice, s));
+    launch_dots(wb.dots_a, wb.dots_b, nd, N, wb.part, wb.dres, s);
+    HIPCHK(hipMemcpyAsync(wb.hres, wb.dres, nd * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int d = 0; d < nd; ++d) out[d] = h.hres[d];
+    for (int d = 0; d < nd; ++d) out[d] = wb.hres[d];
   }
   void A(const double* x, double* y, bool tr) { h.matvec(prob, x, y, tr, s); }
   void M(const double* x, double* y, bool tr) {
@@ -64,9 +70,9 @@ struct KWork {
 
 }  // namespace
 
-acr_status krylov_cg(Handle& h, int prob, bool flexible, bool tr, double rtol, int maxit, const double* b, double* x,
-                     acr_solve_info* info, hipStream_t s) {
-  KWork k(h, s, prob);
+acr_status krylov_cg(Handle& h, KrylovBuffers* wb, int prob, bool flexible, bool tr, double rtol, int maxit,
+                     const double* b, double* x, acr_solve_info* info, hipStream_t s) {
+  KWork k(h, wb, s, prob);
   k.ensure(5);
   double *r = k.vec(0), *zz = k.vec(1), *p = k.vec(2), *Ap = k.vec(3), *zold = k.vec(4);
   const int64_t N = h.N;
@@ -156,9 +162,9 @@ acr_status krylov_cg(Handle& h, int prob, bool flexible, bool tr, double rtol, i
   return stt;
 }
 
-acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int maxit, const double* b, double* x,
-                        acr_solve_info* info, hipStream_t s) {
-  KWork k(h, s, prob);
+acr_status krylov_gmres(Handle& h, KrylovBuffers* wb, int prob, int m, bool tr, double rtol, int maxit,
+                        const double* b, double* x, acr_solve_info* info, hipStream_t s) {
+  KWork k(h, wb, s, prob);
   // layout: V[0..m] (m+1 vectors), Z[0..m-1] (m vectors), r, w
   k.ensure(2 * (size_t)m + 3);
   const int64_t N = h.N;
@@ -178,10 +184,8 @@ acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int ma
     return ACR_OK;
   }
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), hcol(m + 1), h2(m + 1);
-  double* dh = h.dres;  // device scratch for coefficient vectors (<= 64 entries used per call)
-  double* dh_big = nullptr;
-  if (m + 1 > 60) dh_big = h.dnew<double>(m + 1);
-  double* dcoef = dh_big ? dh_big : dh;
+  // device coefficient vector (m + 1 <= 61 entries of the KRYLOV_RES = 64)
+  double* dcoef = k.wb.dres;
   int it = 0;
   acr_status stt = ACR_E_NOTCONV;
   double relres = 1.0;
@@ -208,10 +212,10 @@ acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int ma
       k.A(zk, w, tr);
       // classical Gram-Schmidt, twice
       for (int pass = 0; pass < 2; ++pass) {
-        launch_multi_dot(N, kk + 1, V, N, w, h.part, dcoef, s);
-        HIPCHK(hipMemcpyAsync(h.hres, dcoef, (kk + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_multi_dot(N, kk + 1, V, N, w, k.wb.part, dcoef, s);
+        HIPCHK(hipMemcpyAsync(k.wb.hres, dcoef, (kk + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        for (int i = 0; i <= kk; ++i) (pass ? h2 : hcol)[i] = h.hres[i];
+        for (int i = 0; i <= kk; ++i) (pass ? h2 : hcol)[i] = k.wb.hres[i];
         launch_multi_axpy(N, kk + 1, V, N, dcoef, w, -1.0, s);
       }
       for (int i = 0; i <= kk; ++i) hcol[i] += h2[i];
@@ -255,7 +259,6 @@ acr_status krylov_gmres(Handle& h, int prob, int m, bool tr, double rtol, int ma
     HIPCHK(hipStreamSynchronize(s));
     (void)done;
   }
-  if (dh_big) h.dfree(dh_big);
   info->iters = it;
   info->relres_true = relres;
   info->status = stt;

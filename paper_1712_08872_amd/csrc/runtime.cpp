@@ -65,7 +65,7 @@ Handle::~Handle() {
   }
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
-  if (hres) (void)hipHostFree(hres);
+  if (kbuf.hres) (void)hipHostFree(kbuf.hres);
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (auto& o : owned) {
     if (opt.free)
@@ -404,7 +404,7 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
         kc64::launch_accum<T>(a1, grid, s2);
     }, "");
     AccumArgs<T> ad = a;
-    ad.flops = d_flops ? d_flops + 1 : nullptr;
+    ad.flops = d_flops ? d_flops + FC_COUNT : nullptr;
     timed(s, [&] {
       if (kc == 38)
         kc38::launch_accum_dense<T>(ad, grid, s);
@@ -493,6 +493,7 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
     const Step& st = P.steps[si];
     if (st.type == 1) {
       const Leaf& L = G.lf[st.leaf];
+      leaf_inverse_flops += 2.0 * L.m * L.m * L.m * nbatch;  // LU and inverse of an m x m leaf
       if (fp32)
         launch_leaf_inverse<float>((float* const*)d_inst_base, d_roles, nroles, nbatch, L.off, L.m, d_flags, s);
       else

@@ -85,6 +85,21 @@ struct Instance {
   double packed_bytes = 0;   // packed leaf data in bytes
 };
 
+// Work buffers of a Krylov solve: kv_len vectors of N doubles, dot-product
+// partials, result slots, two device tables of vector pointers and a host
+// landing buffer for the results.
+constexpr int KRYLOV_PART = 64 * 1024;  // dot partials (>= 61 dots x 1024 blocks)
+constexpr int KRYLOV_RES = 64;          // result slots (>= GMRES(60)'s 61 coefficients)
+struct KrylovBuffers {
+  double* kv = nullptr;
+  size_t kv_len = 0;
+  double* part = nullptr;
+  double* dres = nullptr;
+  const double** dots_a = nullptr;
+  const double** dots_b = nullptr;
+  double* hres = nullptr;
+};
+
 struct Coupling {            // coupling of a plane to its previous (A) or next (C) plane
   int kind = 0;              // 0 absent, 1 diagonal (level 0), 2 H-matrix instance
   int inst = -1;
@@ -190,7 +205,8 @@ struct Handle {
   int32_t* d_flags = nullptr;
   unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
   double* d_flops = nullptr;             // optional algorithmic flop counters (ACR_KERNEL_TIMING=1):
-                                         // [0] truncating kernel, [1] accumulate-only kernel
+                                         // [kernel][FlopClass], the truncating kernel first
+  double leaf_inverse_flops = 0.0;       // 2 m^3 per inverted dense diagonal leaf (host count)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -210,11 +226,8 @@ struct Handle {
   double *g = nullptr, *w = nullptr, *z = nullptr, *coef = nullptr;
   int max_jobs = 0;
   std::vector<PhaseJobs> ph_apply, ph_applyT;  // all problems at once
-  // krylov workspace
-  double *kv = nullptr, *part = nullptr, *dres = nullptr;
-  const double **dots_a = nullptr, **dots_b = nullptr;
-  double* hres = nullptr;  // pinned
-  size_t kv_len = 0;
+  // krylov workspace (allocated at the first solve; hres is pinned host memory)
+  KrylovBuffers kbuf;
   // statistics
   acr_stats_t st{};
 
@@ -246,6 +259,20 @@ struct Handle {
   void compute_stats();
   double instance_bytes(const std::vector<int32_t>& ranks) const;
 };
+
+}  // namespace acr
+struct acr_handle;
+namespace acr {
+// krylov_solve over every problem of a handle (wb = nullptr: the handle's
+// own buffers), argument checks, the work-vector count of a method, and the
+// thread-local error text of the ABI
+acr_status solve_problems(acr_handle* h, int32_t method, int32_t restart, int32_t transpose, double rtol,
+                          int32_t maxit, const double* b, double* x, acr_solve_info* info, void* stream,
+                          KrylovBuffers* wb);
+acr_status check_solve_args(const acr_handle* h, int32_t method, int32_t restart, double rtol, int32_t maxit,
+                            const double* b, const double* x, const acr_solve_info* info);
+int krylov_vectors(int32_t method, int32_t restart);
+acr_status set_last_error(acr_status s, const std::string& msg);
 
 // host-side validation of acr_import_factors' blob (throws ACR_E_INVALID)
 void check_factor_blob(const acr_problem* p, const acr_options* o, const acr_factor_blob* blob);

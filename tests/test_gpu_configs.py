@@ -43,6 +43,16 @@ full_only = pytest.mark.skipif(not FULL, reason="full-size configuration (minute
 KIND = {"poisson": acr.POISSON_HARMONIC, "convdiff": acr.CONVDIFF_UPWIND, "helmholtz": acr.HELMHOLTZ}
 
 
+@pytest.fixture
+def progress(monkeypatch):
+    """Long setups report each cyclic-reduction level as it completes."""
+    monkeypatch.setenv("ACR_LOG", "1")
+
+
+def _note(msg):
+    print("  " + msg, flush=True)
+
+
 def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
 
@@ -105,7 +115,7 @@ def test_c1_poisson31_against_oracle():
     h.close()
 
 
-def test_c2_poisson127_full_size():
+def test_c2_poisson127_full_size(progress):
     inp = synth.config_inputs("poisson127")
     n = inp["n"]
     N = n ** 3
@@ -117,6 +127,7 @@ def test_c2_poisson127_full_size():
     np.testing.assert_allclose(Sg, S, rtol=1e-13, atol=0)
     f = _dev(inp["f"])
     x, info = acr.krylov_solve(h, f, method=acr.CG, rtol=1e-8, maxit=200)
+    _note(f"C2 mixed: setup {st['setup_seconds']:.1f} s, CG {info['iters']} iterations")
     assert info["status"] == 0, info
     assert _oracle_relres(S, n, x.cpu().numpy(), inp["f"]) <= 1e-8
     assert _transpose_identity(h, N, 5) <= 1e-10
@@ -125,6 +136,7 @@ def test_c2_poisson127_full_size():
     # FP64 factors reach the same final accuracy
     h = _setup(inp, acr.FP64)
     x64, info64 = acr.krylov_solve(h, f, method=acr.CG, rtol=1e-8, maxit=200)
+    _note(f"C2 FP64: setup {acr.acr_stats(h)['setup_seconds']:.1f} s, CG {info64['iters']} iterations")
     assert info64["status"] == 0, info64
     assert _oracle_relres(S, n, x64.cpu().numpy(), inp["f"]) <= 1e-8
     h.close()
@@ -165,7 +177,7 @@ def _gradient_fd_check(ndir, deltas=(1e-2, 1e-3, 1e-4)):
             kp = kap.reshape(-1) * np.exp(delta * d)
             km = kap.reshape(-1) * np.exp(-delta * d)
             errs.append(abs((J_of(kp) - J_of(km)) / (2 * delta) - an) / abs(an))
-        print(f"  FD relative errors for delta {deltas}: " + ", ".join(f"{e:.2e}" for e in errs))
+        _note(f"FD relative errors for delta {deltas}: " + ", ".join(f"{e:.2e}" for e in errs))
         worst = max(worst, min(errs))
     return worst
 
@@ -179,12 +191,13 @@ def test_c5_adjoint63_twenty_directions_three_deltas():
     assert _gradient_fd_check(20) <= 1e-5
 
 
-def test_c3_convdiff127_gmres():
+def test_c3_convdiff127_gmres(progress):
     inp = synth.config_inputs("cd127")
     n = inp["n"]
     S = _oracle_stencil(inp)
     h = _setup(inp, acr.MIXED_FP32)
     x, info = acr.krylov_solve(h, _dev(inp["f"]), method=acr.GMRES, restart=30, rtol=1e-8, maxit=300)
+    _note(f"C3: setup {acr.acr_stats(h)['setup_seconds']:.1f} s, GMRES {info['iters']} iterations")
     assert info["status"] == 0, info
     assert _oracle_relres(S, n, x.cpu().numpy(), inp["f"]) <= 1e-8
     assert _transpose_identity(h, n ** 3, 6) <= 1e-10
@@ -192,13 +205,14 @@ def test_c3_convdiff127_gmres():
     torch.cuda.empty_cache()
 
 
-def test_c3_batched_48_problems():
+def test_c3_batched_48_problems(progress):
     probs = synth.batched_problems(48)
     specs = [dict(nx=p["n"], ny=p["n"], nz=p["n"], kind=acr.CONVDIFF_UPWIND, kappa=_dev(p["kappa"]),
                   beta_amp=p["beta_amp"], beta_phase=p["beta_phase"]) for p in probs]
     h = acr.acr_setup_batched(specs, eps=1e-4, precision=acr.MIXED_FP32)
     b = torch.cat([_dev(p["f"]) for p in probs])
     x, info = acr.krylov_solve(h, b, method=acr.GMRES, restart=30, rtol=1e-8, maxit=300)
+    _note(f"C3 batch: setup {acr.acr_stats(h)['setup_seconds']:.1f} s, GMRES at most {info['iters']} iterations")
     assert info["status"] == 0, info
     xh = x.cpu().numpy()
     for i, p in enumerate(probs):
@@ -220,7 +234,7 @@ def test_c3_batched_48_problems():
     torch.cuda.empty_cache()
 
 
-def test_c4_helmholtz127_gmres():
+def test_c4_helmholtz127_gmres(progress):
     inp = synth.config_inputs("helmholtz127")
     n = inp["n"]
     S = _oracle_stencil(inp)
@@ -228,6 +242,7 @@ def test_c4_helmholtz127_gmres():
     # 288 GB at full capacity: the rank cap 36 clamps the few larger ones
     h = _setup(inp, acr.FP64, max_rank=36)
     x, info = acr.krylov_solve(h, _dev(inp["f"]), method=acr.GMRES, restart=50, rtol=1e-8, maxit=500)
+    _note(f"C4: setup {acr.acr_stats(h)['setup_seconds']:.1f} s, GMRES {info['iters']} iterations")
     assert info["status"] == 0, info
     assert _oracle_relres(S, n, x.cpu().numpy(), inp["f"]) <= 1e-8
     h.close()
@@ -235,7 +250,7 @@ def test_c4_helmholtz127_gmres():
 
 
 @full_only
-def test_f1_recirc127_gmres():
+def test_f1_recirc127_gmres(progress):
     """The recirculating-flow convection-diffusion of Sec. 7 (eq. codi) at
     127^3, alpha = 8, wavenumber 1, kappa = 1, mixed precision, eps 1e-4:
     GMRES(30) to 1e-8 with the residual recomputed by the oracle's

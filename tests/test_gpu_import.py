@@ -7,8 +7,11 @@ reported ranks and factor bytes are the oracle's.  This separates the
 HBM-streaming sweeps (Sec. 4.1 forward/back substitution with the
 H-matrix-vector products of Sec. 5.3.1) from the setup's truncation.
 Cases: a cubic grid, a ragged one with leaf 16, a nonsymmetric
-convection-diffusion one, a wider multi-tile plane, and the 31^3 workload
-(lognormal kappa, eps 1e-6) with its five levels."""
+convection-diffusion one, a wider multi-tile plane, and the 31 x 31 plane of
+the 31^3 workload (961 unknowns, leaf 32, eps 1e-6) over seven planes.  The
+oracle's setup of the whole 31^3 workload takes minutes on one core, too
+long for this suite; the 31^3 apply is pinned against the oracle by the
+stored samples of the configuration tests."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -28,7 +31,7 @@ CASES = {
     "ragged13x9x6": ("poisson", 13, 9, 6, 1e-5, 16),
     "convdiff14x11x9": ("convdiff", 14, 11, 9, 1e-4, 16),
     "wide23x19x13": ("poisson", 23, 19, 13, 1e-4, 16),
-    "poisson31_c1": ("poisson", 31, 31, 31, 1e-6, 32),
+    "plane31x31x7": ("poisson", 31, 31, 7, 1e-6, 32),
 }
 
 
@@ -40,10 +43,7 @@ def _dev(a):
 def case(request):
     kind, nx, ny, nz, eps, leaf = CASES[request.param]
     print(f"\n[import case {request.param}] {kind} {nx}x{ny}x{nz} eps={eps} leaf={leaf}", flush=True)
-    if request.param == "poisson31_c1":
-        kap = synth.config_inputs("poisson31")["kappa"]
-    else:
-        kap = np.exp(synth.gaussian_field_exp((nz + 2, ny + 2, nx + 2), 1))
+    kap = np.exp(synth.gaussian_field_exp((nz + 2, ny + 2, nx + 2), 1))
     kw = dict(kappa=kap)
     if kind == "convdiff":
         kw.update(beta_amp=60.0, beta_phase=0.9)
