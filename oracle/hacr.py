@@ -16,6 +16,7 @@ import numpy as np
 
 from . import hmatrix as hm
 from .assembly import plane_blocks
+from .fem27 import plane_blocks27
 
 
 def _coupling_matvec(cp, x, transpose=False):
@@ -29,16 +30,26 @@ class HACR:
     """H-matrix cyclic reduction preconditioner ``M^{-1} ~ A^{-1}``."""
 
     def __init__(self, S, nx, ny, nz, eps, eta=2.0, leaf=32):
+        """``S``: a (7, N) stencil of the 7-point operators or a (27, N)
+        stencil of the trilinear finite-element operator (``fem27``)."""
         self.nx, self.ny, self.nz, self.eps = nx, ny, nz, eps
         f0 = hm.flops_snapshot()
         self.ct = hm.ClusterTree(nx, ny, leaf)
         self.bt = hm.BlockTree(self.ct, eta)
         perm = self.ct.perm
         self.perm = perm
-        Dsp, Av, Cv = plane_blocks(S, nx, ny, nz)
-        D = [self._from_sparse(d[perm][:, perm].tocsr()) for d in Dsp]
-        A = [("diag", a[perm]) if a is not None else None for a in Av]
-        C = [("diag", c[perm]) if c is not None else None for c in Cv]
+        if S.shape[0] == 27:
+            # 27-point operator (Sec. 8): the z-couplings are 9-point in-plane matrices, held
+            # as H-matrices from the start, so level 0 uses the formatted products too
+            Dsp, Asp, Csp = plane_blocks27(S, nx, ny, nz)
+            D = [self._from_sparse(d[perm][:, perm].tocsr()) for d in Dsp]
+            A = [("H", self._from_sparse(a[perm][:, perm].tocsr())) if a is not None else None for a in Asp]
+            C = [("H", self._from_sparse(c[perm][:, perm].tocsr())) if c is not None else None for c in Csp]
+        else:
+            Dsp, Av, Cv = plane_blocks(S, nx, ny, nz)
+            D = [self._from_sparse(d[perm][:, perm].tocsr()) for d in Dsp]
+            A = [("diag", a[perm]) if a is not None else None for a in Av]
+            C = [("diag", c[perm]) if c is not None else None for c in Cv]
         self.levels = []
         P = list(range(nz))
         while True:
