@@ -5,6 +5,8 @@ C1  31^3 Poisson, lognormal kappa, FP64, eps 1e-6: M^{-1} f and M^{-T} f
     against the oracle's FP64 H-matrix cyclic reduction (stored by
     tests/golden/make_c1_golden.py), <= 10 eps relative; the CG solution
     against the oracle's sparse direct solution.
+The same recipe at 63^3, FP64 and mixed: M^{-1} f and M^{-T} f against the
+    oracle's stored samples (tests/golden/make_poisson63_golden.py), <= 10 eps.
 C2  127^3 Poisson, 6-decade sub-cube kappa, eps 1e-4, mixed precision: the
     assembled stencil against the oracle's assembly; CG to 1e-8 with the
     true residual recomputed on the CPU by the oracle's operator; the
@@ -112,6 +114,36 @@ def test_c1_poisson31_against_oracle():
     assert info["status"] == 0 and info["iters"] <= 5
     xs = x.cpu().numpy()[idx]
     assert np.max(np.abs(xs - np.array(g["x"]))) <= 1e-8 * np.max(np.abs(g["x"]))
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [acr.FP64, acr.MIXED_FP32], ids=["fp64", "mixed"])
+def test_poisson63_subcube_against_oracle(precision):
+    """The recipe of the 127^3 workload at 63^3 (sub-cube kappa of six
+    decades, eps 1e-4; 4,096-leaf-cluster planes, 6 levels): M^{-1} f and
+    M^{-T} f against the oracle's FP64 H-matrix cyclic reduction (stored by
+    tests/golden/make_poisson63_golden.py) at 2,048 sampled entries, in the
+    root-mean-square and the largest entry, and the 2-norm: within 10 eps."""
+    g = json.load(open(os.path.join(HERE, "golden", "poisson63_subcube.json")))
+    n, eps = g["n"], g["eps"]
+    kap = synth.kappa_subcubes(n, g["kappa_seed"])
+    f = synth.rhs_uniform(n ** 3, g["f_seed"])
+    idx = np.array(g["index"])
+    h = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=_dev(kap), eps=eps, eta=g["eta"], leaf_size=g["leaf"],
+                      precision=precision)
+    for key, fn in (("z", acr.acr_apply), ("zt", acr.acr_apply_T)):
+        mine = fn(h, _dev(f)).cpu().numpy()
+        ref = np.array(g[key])
+        rms = np.sqrt(np.mean((mine[idx] - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+        emax = np.max(np.abs(mine[idx] - ref)) / g[key + "_max"]
+        enorm = abs(np.linalg.norm(mine) - g[key + "_norm"]) / g[key + "_norm"]
+        _note(f"63^3 {key}: rms {rms:.2e}, max {emax:.2e}, norm {enorm:.2e} (oracle vs exact "
+              f"{g['oracle_vs_exact']:.1e})")
+        assert rms <= 10 * eps and emax <= 10 * eps and enorm <= 10 * eps, (key, rms, emax, enorm)
+    x, info = acr.krylov_solve(h, _dev(f), method=acr.CG, rtol=1e-12, maxit=300)
+    xe = np.max(np.abs(x.cpu().numpy()[idx] - np.array(g["x"]))) / np.max(np.abs(g["x"]))
+    _note(f"63^3 CG to 1e-12: {info['iters']} iterations, largest sampled error {xe:.2e}")
+    assert info["status"] == 0 and xe <= 1e-6
     h.close()
 
 
