@@ -233,6 +233,24 @@ acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t 
                         double rtol, int32_t maxit, const double* b, double* x,
                         acr_solve_info* info, void* stream);
 
+/* krylov_solve without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, semantics and results as
+ * krylov_solve, but the Krylov work vectors, the dot-product partials and
+ * the result slots live in a fixed array of ACR_STATIC_WORKSPACE_BYTES in
+ * the library's device code object (one per GPU, held until the process
+ * ends) instead of memory the handle allocates at its first solve; the call
+ * allocates no device or pinned host memory.  The handle itself is made by
+ * acr_setup, which allocates.  CG/FCG need 5 vectors of the largest
+ * problem's N doubles, GMRES(m) 2m + 3; ACR_E_INVALID if they do not fit
+ * (CG fits up to about 3.3 million unknowns per problem, GMRES(30) up to
+ * about 266 thousand).  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (concurrent host threads or streams) race. */
+#define ACR_STATIC_WORKSPACE_BYTES (128u << 20)
+
+acr_status krylov_solve_static(acr_handle* h, int32_t method, int32_t restart, int32_t transpose, double rtol,
+                               int32_t maxit, const double* b, double* x, acr_solve_info* info, void* stream);
+
 /* Adjoint gradient for ACR_POISSON_HARMONIC: dkappa = -lam^T (dA/dkappa) u
  * on the node grid ((nz+2)(ny+2)(nx+2) doubles, overwritten). */
 acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa,

@@ -105,7 +105,7 @@ class GeometryInfo(ctypes.Structure):
 SYMBOLS = ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_num_problems", "acr_apply", "acr_apply_T",
            "acr_matvec", "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_destroy",
            "acr_status_string", "acr_last_error", "acr_default_options", "acr_plane_geometry",
-           "acr_import_factors"]
+           "acr_import_factors", "krylov_solve_static"]
 
 _lib = None
 
@@ -133,6 +133,7 @@ def lib():
     L.acr_matvec.argtypes = [vp, i32, vp, vp, vp]
     L.acr_get_stencil.argtypes = [vp, vp, vp]
     L.krylov_solve.argtypes = [vp, i32, i32, i32, dbl, i32, vp, vp, ctypes.POINTER(SolveInfo), vp]
+    L.krylov_solve_static.argtypes = [vp, i32, i32, i32, dbl, i32, vp, vp, ctypes.POINTER(SolveInfo), vp]
     L.acr_grad_kappa.argtypes = [vp, vp, vp, vp, vp]
     L.acr_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.acr_destroy.argtypes = [vp]
@@ -146,7 +147,8 @@ def lib():
     L.acr_default_options.argtypes = [ctypes.POINTER(Options)]
     L.acr_default_options.restype = None
     for name in ["acr_setup", "acr_setup_batched", "acr_problem_offset", "acr_apply", "acr_apply_T", "acr_matvec",
-                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_plane_geometry", "acr_import_factors"]:
+                 "acr_get_stencil", "krylov_solve", "acr_grad_kappa", "acr_stats", "acr_plane_geometry", "acr_import_factors",
+                 "krylov_solve_static"]:
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -304,14 +306,17 @@ def acr_get_stencil(h, stream=None):
 
 
 def krylov_solve(h, b, x=None, method=CG, restart=30, transpose=False, rtol=1e-8, maxit=1000, stream=None,
-                 raise_on_fail=True):
-    """Returns ``(x, info_dict)``."""
+                 raise_on_fail=True, static_workspace=False):
+    """Returns ``(x, info_dict)``.  ``static_workspace=True`` calls
+    ``krylov_solve_static`` (the work vectors in the library's fixed device
+    array; no allocation by the library)."""
     import torch
     x = torch.zeros_like(b) if x is None else x
     _need(b, h.total, "b")
     _need(x, h.total, "x")
     info = SolveInfo()
-    st = lib().krylov_solve(h.ptr, method, restart, int(transpose), rtol, maxit, _ptr(b), _ptr(x),
+    fn = lib().krylov_solve_static if static_workspace else lib().krylov_solve
+    st = fn(h.ptr, method, restart, int(transpose), rtol, maxit, _ptr(b), _ptr(x),
                             ctypes.byref(info), _stream(stream))
     d = {"iters": info.iters, "relres_true": info.relres_true, "status": info.status, "variant": info.variant}
     if st != 0 and raise_on_fail:

@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libacr.so")
 # two round widths
 SOURCES = [("k_harith.hip", ["-DKCV=64"], "k_harith_64"), ("k_harith.hip", ["-DKCV=38"], "k_harith_38"),
            ("k_apply.hip", [], "k_apply"), ("k_vec.hip", [], "k_vec"), ("geometry.cpp", [], "geometry"),
-           ("program.cpp", [], "program"), ("runtime.cpp", [], "runtime"), ("cr.cpp", [], "cr"), ("import.cpp", [], "import"), ("krylov.cpp", [], "krylov"),
+           ("program.cpp", [], "program"), ("runtime.cpp", [], "runtime"), ("cr.cpp", [], "cr"), ("import.cpp", [], "import"), ("krylov.cpp", [], "krylov"), ("static_ws.cpp", [], "static_ws"),
            ("api.cpp", [], "api")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
