@@ -35,4 +35,5 @@ def test_one_iteration_residual_shrinks_with_eps():
     vals = [res[e] for e in (1e-4, 1e-5, 1e-6, 1e-7)]
     # each decade of eps buys at least half a decade of residual
     assert all(b < a / 3 for a, b in zip(vals, vals[1:])), vals
-    assert res[1e-7] <= 1e-5, res
+    # at the smallest accepted eps one iteration already meets the paper's 1e-8 (measured 4.6e-9)
+    assert res[1e-7] <= 1e-8, res
