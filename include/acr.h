@@ -60,10 +60,16 @@ typedef enum {
     ACR_CONVDIFF_UPWIND = 1,  /* -div(kappa grad u) + beta.grad u, first-order upwind (Sec. 7) */
     ACR_HELMHOLTZ = 2,        /* -Lap u - (omega/c)^2 u, 7-point (Sec. 8, FD variant) */
     ACR_STENCIL7_RAW = 3,     /* caller-provided 7-point stencil */
-    ACR_CONVDIFF_RECIRC = 4   /* -div(kappa grad u) + alpha b(x).grad u with the divergence-free
+    ACR_CONVDIFF_RECIRC = 4,  /* -div(kappa grad u) + alpha b(x).grad u with the divergence-free
                                  recirculating flow b of Sec. 7 (eq. codi), wavenumber a:
                                  beta_amp = alpha, beta_phase = a; first-order upwind per
                                  direction at the node */
+    ACR_HELMHOLTZ_FEM27 = 5   /* -Lap u - (omega/c)^2 u discretised by continuous trilinear finite
+                                 elements on the hexahedral grid (Sec. 8, eq. HelmVarVel: the
+                                 27-point scheme): Q1 stiffness minus the mass weighted by
+                                 omega^2/c^2, integrated by the 2x2x2 Gauss rule with c (node
+                                 grid) interpolated trilinearly; the plane couplings are 9-point
+                                 in-plane matrices, held as H-matrices from level 0 on */
 } acr_kind;
 
 typedef enum {
@@ -71,13 +77,14 @@ typedef enum {
     ACR_MIXED_FP32 = 1, /* factors stored and multiplied in FP32; leaf
                            inversion, Gram matrices, core eigen/SVD and
                            Krylov in FP64 */
-    ACR_MIXED_BF16 = 2  /* setup as ACR_MIXED_FP32, then the stored factors
-                           are rounded to BF16 (8-bit mantissa, nearest
-                           even), halving the bytes the apply streams;
-                           apply arithmetic in FP64.  Only for eps >= 1e-2
-                           (ACR_E_INVALID otherwise): the rounding error,
-                           about 4e-3 relative per entry, must stay below
-                           the truncation accuracy */
+    ACR_MIXED_BF16 = 2  /* as ACR_MIXED_FP32, with the piece products of the
+                           setup's H-arithmetic on the BF16 matrix cores:
+                           their operands are rounded to BF16 (8-bit
+                           mantissa, nearest even) and accumulated in FP32;
+                           factors stored in FP32.  Only for eps >= 1e-2
+                           (ACR_E_INVALID otherwise): the rounding, about
+                           4e-3 relative per operand, must stay below the
+                           truncation accuracy */
 } acr_precision;
 
 typedef enum { ACR_CG = 0, ACR_FCG = 1, ACR_GMRES = 2 } acr_method;
@@ -215,11 +222,14 @@ acr_status acr_apply(acr_handle* h, const double* r, double* z, int32_t nrhs, vo
 acr_status acr_apply_T(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* y = A x (transpose = 0) or A^T x (transpose = 1) with the assembled
- * 7-point operator; x, y device, N doubles. */
+ * operator (7- or 27-point); x, y device, N doubles. */
 acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double* y, void* stream);
 
-/* Copy the assembled stencil (7*N doubles, layout of acr_problem.stencil7)
- * to the device buffer out. */
+/* Copy the assembled stencil to the device buffer out: 7*N doubles in the
+ * layout of acr_problem.stencil7, or for ACR_HELMHOLTZ_FEM27 27*N doubles,
+ * row m = (dx+1) + 3 (dy+1) + 9 (dz+1) holding the coupling to the
+ * neighbour at offset (dx, dy, dz) (row 13 the centre).  A batched handle
+ * writes its problems one after another, each with its own row count. */
 acr_status acr_get_stencil(acr_handle* h, double* out, void* stream);
 
 /* Preconditioned Krylov solve of A x = b (or A^T x = b when transpose=1,
@@ -289,6 +299,9 @@ typedef struct {
 
 acr_status acr_plane_geometry(int32_t nx, int32_t ny, const acr_options* o, acr_geometry_info* info,
                               int32_t* perm, int32_t* leaves, int32_t leaves_cap);
+/* (The geometry is that of the 7-point operators; with ACR_HELMHOLTZ_FEM27
+ * an admissible leaf holding a diagonal in-plane coupling is also stored
+ * dense, which happens only for eta above about 5.) */
 
 /* ---- Test hook: factors built elsewhere (e.g. by a CPU reference) ----
  *

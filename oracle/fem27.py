@@ -144,11 +144,13 @@ def plane_blocks27(S, nx, ny, nz):
     return D, A, C
 
 
-def waveguide_velocity(n):
-    """The waveguide velocity of eq. HelmVarVel on the (n+2)^3 node grid:
-    ``c = 1.25 (1 - 0.4 exp(-32 ((x - 1/2)^2 + (y - 1/2)^2)))``."""
-    t = np.arange(n + 2) / (n + 1)
-    z, y, x = np.meshgrid(t, t, t, indexing="ij")
+def waveguide_velocity(nx, ny=None, nz=None):
+    """The waveguide velocity of eq. HelmVarVel on the (nz+2, ny+2, nx+2)
+    node grid: ``c = 1.25 (1 - 0.4 exp(-32 ((x - 1/2)^2 + (y - 1/2)^2)))``."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    z, y, x = np.meshgrid(np.arange(nz + 2) / (nz + 1), np.arange(ny + 2) / (ny + 1), np.arange(nx + 2) / (nx + 1),
+                          indexing="ij")
     return 1.25 * (1.0 - 0.4 * np.exp(-32.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2)))
 
 

@@ -17,7 +17,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacr.so")
 
-POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW, CONVDIFF_RECIRC = 0, 1, 2, 3, 4
+POISSON_HARMONIC, CONVDIFF_UPWIND, HELMHOLTZ, STENCIL7_RAW, CONVDIFF_RECIRC, HELMHOLTZ_FEM27 = 0, 1, 2, 3, 4, 5
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 CG, FCG, GMRES = 0, 1, 2
 MAX_LEVELS = 32
@@ -207,10 +207,11 @@ class Handle:
     grid_N) per problem; ``total``/``grid_total`` are the concatenated
     lengths."""
 
-    def __init__(self, ptr, n, keep):
+    def __init__(self, ptr, n, keep, kinds=None):
         self.ptr = ptr
         self.n = n
         self._keep = keep
+        self.kinds = list(kinds) if kinds is not None else []
         L = lib()
         self.offsets = []
         for i in range(L.acr_num_problems(ptr)):
@@ -219,6 +220,9 @@ class Handle:
             self.offsets.append((a.value, b.value, c.value, d.value))
         self.total = sum(o[1] for o in self.offsets)
         self.grid_total = sum(o[3] for o in self.offsets)
+        # stencil rows per unknown of each problem (27 for the finite-element operator)
+        self.stencil_total = sum((27 if k == HELMHOLTZ_FEM27 else 7) * o[1]
+                                 for k, o in zip(self.kinds or [POISSON_HARMONIC] * len(self.offsets), self.offsets))
 
     def __del__(self):
         self.close()
@@ -242,7 +246,7 @@ def acr_setup(nx, ny, nz, kind=POISSON_HARMONIC, kappa=None, beta_amp=0.0, beta_
                         dense_work=dense_work)
     out = ctypes.c_void_p()
     _check(lib().acr_setup(ctypes.byref(p), ctypes.byref(o), _stream(stream), ctypes.byref(out)))
-    return Handle(out, (nx, ny, nz), (kappa, c, stencil7))
+    return Handle(out, (nx, ny, nz), (kappa, c, stencil7), [kind])
 
 
 def acr_setup_batched(problems, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64, max_rank=0, dense_work=0,
@@ -263,7 +267,7 @@ def acr_setup_batched(problems, eps=1e-4, eta=2.0, leaf_size=32, precision=FP64,
                         dense_work=dense_work)
     out = ctypes.c_void_p()
     _check(lib().acr_setup_batched(arr, len(problems), ctypes.byref(o), _stream(stream), ctypes.byref(out)))
-    return Handle(out, None, keep)
+    return Handle(out, None, keep, [d.get("kind", POISSON_HARMONIC) for d in problems])
 
 
 def _nrhs(h, r, z):
@@ -300,7 +304,7 @@ def acr_matvec(h, x, transpose=False, y=None, stream=None):
 
 def acr_get_stencil(h, stream=None):
     import torch
-    out = torch.empty(7 * h.total, dtype=torch.float64, device="cuda")
+    out = torch.empty(h.stencil_total, dtype=torch.float64, device="cuda")
     _check(lib().acr_get_stencil(h.ptr, _ptr(out), _stream(stream)))
     return out
 
@@ -367,7 +371,7 @@ def acr_import_factors(nx, ny, nz, factors, kind=POISSON_HARMONIC, kappa=None, b
     out = ctypes.c_void_p()
     _check(lib().acr_import_factors(ctypes.byref(p), ctypes.byref(o), ctypes.byref(blob), _stream(stream),
                                     ctypes.byref(out)))
-    return Handle(out, (nx, ny, nz), (kappa, c, stencil7))
+    return Handle(out, (nx, ny, nz), (kappa, c, stencil7), [kind])
 
 
 def acr_plane_geometry(nx, ny, eta=2.0, leaf_size=32, dense_work=0, eps=1e-4):

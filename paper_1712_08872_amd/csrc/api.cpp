@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <exception>
 #include <string>
+#include <thread>
 #include <tuple>
 
 #include "runtime.h"
@@ -63,9 +65,9 @@ acr_status check_problem(const acr_problem* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(ACR_E_INVALID, "grid sizes must be >= 1");
   if ((int64_t)p->nx * p->ny > (1 << 26) || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34))
     return fail(ACR_E_INVALID, "grid too large");
-  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_CONVDIFF_RECIRC) return fail(ACR_E_INVALID, "unknown problem kind");
+  if (p->kind < ACR_POISSON_HARMONIC || p->kind > ACR_HELMHOLTZ_FEM27) return fail(ACR_E_INVALID, "unknown problem kind");
   if (p->kind == ACR_STENCIL7_RAW && !p->stencil7) return fail(ACR_E_INVALID, "RAW problem needs stencil7");
-  if (p->kind == ACR_HELMHOLTZ && (!p->c || !std::isfinite(p->omega)))
+  if ((p->kind == ACR_HELMHOLTZ || p->kind == ACR_HELMHOLTZ_FEM27) && (!p->c || !std::isfinite(p->omega)))
     return fail(ACR_E_INVALID, "Helmholtz problem needs c and a finite omega");
   if ((p->kind == ACR_CONVDIFF_UPWIND || p->kind == ACR_CONVDIFF_RECIRC) &&
       (!std::isfinite(p->beta_amp) || !std::isfinite(p->beta_phase)))
@@ -99,10 +101,11 @@ acr_status setup_many(const acr_problem* ps, int count, const acr_options* o, vo
   acr_handle* h = nullptr;
   acr_status st = guard([&]() {
     h = new acr_handle();
-    std::map<std::tuple<int, int, int>, int> gid;
+    std::map<std::tuple<int, int, int, int>, int> gid;
     std::vector<std::vector<int>> members;
     for (int i = 0; i < count; ++i) {
-      auto key = std::make_tuple(ps[i].nx, ps[i].ny, ps[i].nz);
+      // a group shares the plane shape and the stencil (7- or 27-point)
+      auto key = std::make_tuple(ps[i].nx, ps[i].ny, ps[i].nz, ps[i].kind == ACR_HELMHOLTZ_FEM27 ? 27 : 7);
       auto it = gid.find(key);
       int g;
       if (it == gid.end()) {
@@ -121,14 +124,64 @@ acr_status setup_many(const acr_problem* ps, int count, const acr_options* o, vo
       h->total += (int64_t)ps[i].nx * ps[i].ny * ps[i].nz;
       h->grid_total += (int64_t)(ps[i].nx + 2) * (ps[i].ny + 2) * (ps[i].nz + 2);
     }
-    for (auto& mem : members) {
-      std::vector<acr_problem> group;
-      for (int i : mem) group.push_back(ps[i]);
-      auto grp = std::make_unique<acr::Handle>();
-      grp->opt = *o;
-      grp->setup(group.data(), (int)group.size(), (hipStream_t)stream);
-      h->groups.push_back(std::move(grp));
+    const int G = (int)members.size();
+    std::vector<std::vector<acr_problem>> gp(G);
+    for (int g = 0; g < G; ++g) {
+      for (int i : members[g]) gp[g].push_back(ps[i]);
+      h->groups.push_back(std::make_unique<acr::Handle>());
+      h->groups.back()->opt = *o;
     }
+    if (G == 1) {
+      h->groups[0]->setup(gp[0].data(), (int)gp[0].size(), (hipStream_t)stream);
+      return ACR_OK;
+    }
+    // several plane shapes: each group on its own stream (forked from the
+    // caller's, so the inputs are ready) and host thread, concurrently when
+    // their estimated setup footprints fit the free device memory together
+    // (about 400 bytes per unknown and unit of rank capacity and per byte of
+    // factor precision, the measured peak of the 127^3 setups with margin)
+    HIPCHK(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->fork, (hipStream_t)stream));
+    for (int g = 0; g < G; ++g) {
+      hipStream_t gs;
+      hipEvent_t ge;
+      HIPCHK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+      h->gstream.push_back(gs);
+      HIPCHK(hipEventCreateWithFlags(&ge, hipEventDisableTiming));
+      h->gdone.push_back(ge);
+      HIPCHK(hipStreamWaitEvent(gs, h->fork, 0));
+    }
+    const double cap = o->max_rank > 0 ? o->max_rank : std::max(8.0, 6.0 + 6.0 * std::log10(1.0 / o->eps));
+    const double esz = o->precision == ACR_FP64 ? 8.0 : 4.0;
+    double est = 0.0;
+    for (int g = 0; g < G; ++g)
+      est += 400.0 * cap * esz * (double)gp[g][0].nx * gp[g][0].ny * gp[g][0].nz * (double)gp[g].size();
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const bool serial = est > 0.7 * (double)free_b || [] {
+      const char* e = getenv("ACR_SERIAL_GROUPS");
+      return e && e[0] == '1';
+    }();
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::vector<std::exception_ptr> err(G);
+    auto run = [&](int g) {
+      try {
+        HIPCHK(hipSetDevice(dev));
+        h->groups[g]->setup(gp[g].data(), (int)gp[g].size(), h->gstream[g]);
+      } catch (...) {
+        err[g] = std::current_exception();
+      }
+    };
+    if (serial) {
+      for (int g = 0; g < G; ++g) run(g);
+    } else {
+      std::vector<std::thread> th;
+      for (int g = 0; g < G; ++g) th.emplace_back(run, g);
+      for (auto& t : th) t.join();
+    }
+    for (int g = 0; g < G; ++g)
+      if (err[g]) std::rethrow_exception(err[g]);
     return ACR_OK;
   });
   if (st != ACR_OK) {
@@ -155,6 +208,37 @@ void for_groups(acr_handle* h, const double* r, double* z, F&& f) {
     f(grp, in, outp);
   }
 }
+// z = M^{-1} r or M^{-T} r for every problem: one group on the caller's
+// stream; several groups each on its own stream, forked from and joined to
+// the caller's (stream-ordered for the caller, concurrent between groups).
+acr_status apply_all(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream, bool tr) {
+  if (!h || !r || !z) return fail(ACR_E_INVALID, "null argument");
+  if (nrhs < 1) return fail(ACR_E_INVALID, "nrhs must be >= 1");
+  if (r == z) return fail(ACR_E_INVALID, "z must not alias r");
+  return guard([&]() {
+    const bool fork = !h->gstream.empty();
+    if (fork) {
+      HIPCHK(hipEventRecord(h->fork, (hipStream_t)stream));
+      for (hipStream_t gs : h->gstream) HIPCHK(hipStreamWaitEvent(gs, h->fork, 0));
+    }
+    size_t gi = 0;
+    for (int k = 0; k < nrhs; ++k) {
+      gi = 0;
+      for_groups(h, r + (int64_t)k * h->total, z + (int64_t)k * h->total,
+                 [&](acr::Handle& g, const std::vector<const double*>& in, const std::vector<double*>& outp) {
+                   g.apply(in, outp, tr, -1, fork ? h->gstream[gi] : (hipStream_t)stream);
+                   ++gi;
+                 });
+    }
+    if (fork)
+      for (size_t g = 0; g < h->gstream.size(); ++g) {
+        HIPCHK(hipEventRecord(h->gdone[g], h->gstream[g]));
+        HIPCHK(hipStreamWaitEvent((hipStream_t)stream, h->gdone[g], 0));
+      }
+    return ACR_OK;
+  });
+}
+
 }  // namespace
 
 namespace acr {
@@ -321,31 +405,11 @@ acr_status acr_problem_offset(const acr_handle* h, int32_t i, int64_t* off, int6
 }
 
 acr_status acr_apply(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream) {
-  if (!h || !r || !z) return fail(ACR_E_INVALID, "null argument");
-  if (nrhs < 1) return fail(ACR_E_INVALID, "nrhs must be >= 1");
-  if (r == z) return fail(ACR_E_INVALID, "z must not alias r");
-  return guard([&]() {
-    for (int k = 0; k < nrhs; ++k)
-      for_groups(h, r + (int64_t)k * h->total, z + (int64_t)k * h->total,
-                 [&](acr::Handle& g, const std::vector<const double*>& in, const std::vector<double*>& outp) {
-                   g.apply(in, outp, false, -1, (hipStream_t)stream);
-                 });
-    return ACR_OK;
-  });
+  return apply_all(h, r, z, nrhs, stream, false);
 }
 
 acr_status acr_apply_T(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream) {
-  if (!h || !r || !z) return fail(ACR_E_INVALID, "null argument");
-  if (nrhs < 1) return fail(ACR_E_INVALID, "nrhs must be >= 1");
-  if (r == z) return fail(ACR_E_INVALID, "z must not alias r");
-  return guard([&]() {
-    for (int k = 0; k < nrhs; ++k)
-      for_groups(h, r + (int64_t)k * h->total, z + (int64_t)k * h->total,
-                 [&](acr::Handle& g, const std::vector<const double*>& in, const std::vector<double*>& outp) {
-                   g.apply(in, outp, true, -1, (hipStream_t)stream);
-                 });
-    return ACR_OK;
-  });
+  return apply_all(h, r, z, nrhs, stream, true);
 }
 
 acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double* y, void* stream) {
@@ -362,10 +426,12 @@ acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double*
 acr_status acr_get_stencil(acr_handle* h, double* out, void* stream) {
   if (!h || !out) return fail(ACR_E_INVALID, "null argument");
   return guard([&]() {
+    int64_t o = 0;
     for (size_t i = 0; i < h->where.size(); ++i) {
       const acr::Handle& g = *h->groups[h->where[i].first];
-      HIPCHK(hipMemcpyAsync(out + 7 * h->off[i], g.probs[h->where[i].second].S, 7 * g.N * sizeof(double),
+      HIPCHK(hipMemcpyAsync(out + o, g.probs[h->where[i].second].S, g.nst() * g.N * sizeof(double),
                             hipMemcpyDeviceToDevice, (hipStream_t)stream));
+      o += g.nst() * g.N;
     }
     return ACR_OK;
   });

@@ -84,6 +84,7 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
   N = (int64_t)B * nz;
   fp32 = opt.precision == ACR_MIXED_FP32 || opt.precision == ACR_MIXED_BF16;
   bf16 = opt.precision == ACR_MIXED_BF16;
+  fem27 = ps[0].kind == ACR_HELMHOLTZ_FEM27;
   const int64_t M = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
   d_flags = dnew<int32_t>(FL_COUNT);
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
@@ -105,10 +106,14 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
     P.beta_amp = p->beta_amp;
     P.beta_phase = p->beta_phase;
     P.omega = p->omega;
-    P.S = dnew<double>(7 * N);
+    P.S = dnew<double>((size_t)nst() * N);
     if (P.kind == ACR_STENCIL7_RAW) {
       HIPCHK(hipMemcpyAsync(P.S, p->stencil7, 7 * N * sizeof(double), hipMemcpyDeviceToDevice, s));
       launch_check(P.S, 7 * N, 0, d_flags + FL_NONFINITE, s);
+    } else if (P.kind == ACR_HELMHOLTZ_FEM27) {
+      launch_check(p->c, M, 1, d_flags + FL_NONFINITE, s);
+      launch_assemble27(nx, ny, nz, p->c, P.omega, P.S, s);
+      launch_check(P.S, 27 * N, 0, d_flags + FL_NONFINITE, s);
     } else {
       if (p->kappa) {
         P.kappa = dnew<double>(M);
@@ -129,7 +134,7 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
   if (hflags[FL_NONFINITE]) throw AcrError(ACR_E_NUMERIC, "non-finite or non-positive coefficient");
 
   // ---- geometry and its device tables
-  G = build_geometry(nx, ny, opt.leaf_size, opt.eta, opt.dense_work);
+  G = build_geometry(nx, ny, opt.leaf_size, opt.eta, opt.dense_work, fem27);
   d_perm = upload(G.perm);
   {
     std::vector<int32_t> seg_lo, rp{0}, ri, cp{0}, ci;
@@ -147,27 +152,29 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
     d_cols_ptr = upload(cp);
     d_cols_idx = upload(ci);
   }
-  for (Prob& P : probs) {
-    P.zA = dnew<double>(N);
-    P.zC = dnew<double>(N);
-    launch_zcoupling(P.S, N, B, nz, d_perm, P.zA, P.zC, s);
-  }
+  if (!fem27)
+    for (Prob& P : probs) {
+      P.zA = dnew<double>(N);
+      P.zC = dnew<double>(N);
+      launch_zcoupling(P.S, N, B, nz, d_perm, P.zA, P.zC, s);
+    }
 }
 
-// After the factors exist: release the setup's working memory, round to
-// BF16 if asked, build and tune the apply phases, and gather statistics.
+// After the factors exist: release the setup's working memory, build and
+// tune the apply phases, and gather statistics.
 void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start) {
   // working memory of the setup: recycled capacity buffers and the
   // accumulation scratch
   HIPCHK(hipStreamSynchronize(s));
   for (void* b : cap_pool) dfree(b);
   cap_pool.clear();
-  if (scratch) {
-    dfree(scratch);
-    scratch = nullptr;
-    scratch_stride = 0;
+  for (Lane& ln : lanes) {
+    if (ln.scratch) dfree(ln.scratch);
+    if (ln.dbuf) dfree(ln.dbuf);
+    ln.scratch = ln.dbuf = nullptr;
+    ln.dbuf_bytes = 0;
   }
-  if (bf16) round_factors_bf16(s);
+  scratch_stride = 0;
   build_apply_jobs();
   tune_apply(s);
   HIPCHK(hipStreamSynchronize(s));
@@ -302,7 +309,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
   upload_leaf_tables();
   {
     // level-0 scatter map: in-plane couplings -> dense leaf entries
-    std::vector<int64_t> map(5 * (size_t)B, -1);
+    std::vector<int64_t> map;
     std::vector<int> pos(B);
     for (int i = 0; i < B; ++i) pos[G.perm[i]] = i;
     auto find_leaf = [&](int i, int j) {
@@ -315,11 +322,21 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       }
       return G.bn[nd].leaf;
     };
-    const int dxs[5] = {0, -1, 1, 0, 0}, dys[5] = {0, 0, 0, -1, 1};
+    // in-plane offsets of the scatter map: the 5-point star (centre, x-1,
+    // x+1, y-1, y+1: stencil rows 0..4) or all 9 offsets d = (dx+1) + 3 (dy+1)
+    // of the 27-point operator
+    const int nd = fem27 ? 9 : 5;
+    int dxs[9], dys[9];
+    for (int d = 0; d < nd; ++d) {
+      const int sx5[5] = {0, -1, 1, 0, 0}, sy5[5] = {0, 0, 0, -1, 1};
+      dxs[d] = fem27 ? d % 3 - 1 : sx5[d];
+      dys[d] = fem27 ? d / 3 - 1 : sy5[d];
+    }
+    map.assign((size_t)nd * B, -1);
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int i = pos[x + nx * y];
-        for (int d = 0; d < 5; ++d) {
+        for (int d = 0; d < nd; ++d) {
           int xx = x + dxs[d], yy = y + dys[d];
           if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) continue;
           int j = pos[xx + nx * yy];
@@ -340,13 +357,17 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     kc = (*std::max_element(caps.begin(), caps.end()) <= 30) ? 38 : 64;
     int64_t stride = (int64_t)(mm + nn) * kc + DACC_ELEMS;  // + dense accumulator of small low-rank targets
     stride = ((stride + 63) / 64) * 64;
-    if (stride > scratch_stride || !scratch) {
-      if (scratch) dfree(scratch);
+    if (stride > scratch_stride) {
+      for (Lane& ln : lanes)
+        if (ln.scratch) {
+          dfree(ln.scratch);
+          ln.scratch = nullptr;
+        }
       scratch_slots = 2048;
       scratch_stride = stride;
-      // two regions: the main stream's and the second stream's launches
-      scratch = dmalloc((size_t)2 * scratch_slots * stride * (fp32 ? 4 : 8));
     }
+    // two regions per lane: its main stream's and its second stream's launches
+    ensure_lane(lanes[0], s);
   }
 
   // ---- level 0: the plane operators D_k as H-matrices
@@ -356,21 +377,52 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     for (int k = 0; k < nz; ++k) P.plane_inst[k] = new_instance(s);
   }
   sync_tables();
-  for (Prob& P : probs) {
-    int32_t* d_pi = upload(P.plane_inst);
+  // stencil rows of the in-plane entries of the scatter map: D (dz = 0), and
+  // for the 27-point operator also A (dz = -1) and C (dz = +1)
+  auto l0rows = [&](int dz) {
+    L0Rows r{};
+    r.nd = fem27 ? 9 : 5;
+    for (int d = 0; d < r.nd; ++d) r.row[d] = fem27 ? d + 9 * (dz + 1) : d;
+    return r;
+  };
+  auto fill = [&](const Prob& P, const std::vector<int>& ids, int plane0, int dz) {
+    int32_t* d_ids = upload(std::vector<int32_t>(ids.begin(), ids.end()));
+    sync_tables();
     if (fp32)
-      launch_level0<float>((float* const*)d_inst_base, d_pi, nz, 0, P.S, N, B, d_perm, d_l0map, s);
+      launch_level0<float>((float* const*)d_inst_base, d_ids, (int)ids.size(), plane0, P.S, N, B, d_perm, d_l0map,
+                           l0rows(dz), s);
     else
-      launch_level0<double>((double* const*)d_inst_base, d_pi, nz, 0, P.S, N, B, d_perm, d_l0map, s);
+      launch_level0<double>((double* const*)d_inst_base, d_ids, (int)ids.size(), plane0, P.S, N, B, d_perm,
+                            d_l0map, l0rows(dz), s);
     HIPCHK(hipStreamSynchronize(s));
-    dfree(d_pi);
-  }
+    dfree(d_ids);
+  };
+  for (Prob& P : probs) fill(P, P.plane_inst, 0, 0);
   std::vector<std::vector<Coupling>> Acur(np, std::vector<Coupling>(nz)), Ccur(np, std::vector<Coupling>(nz));
-  for (int q = 0; q < np; ++q)
-    for (int k = 0; k < nz; ++k) {
-      if (k > 0) Acur[q][k] = Coupling{1, -1, probs[q].zA + (int64_t)k * B};
-      if (k < nz - 1) Ccur[q][k] = Coupling{1, -1, probs[q].zC + (int64_t)k * B};
-    }
+  if (!fem27) {
+    for (int q = 0; q < np; ++q)
+      for (int k = 0; k < nz; ++k) {
+        if (k > 0) Acur[q][k] = Coupling{1, -1, probs[q].zA + (int64_t)k * B};
+        if (k < nz - 1) Ccur[q][k] = Coupling{1, -1, probs[q].zC + (int64_t)k * B};
+      }
+  } else {
+    // the 9-point z-coupling planes as H-matrices (exact: their entries lie in
+    // dense leaves), final at once: built and packed a chunk at a time so that
+    // only a few capacity buffers are live
+    constexpr int kChunk = 16;
+    for (int q = 0; q < np; ++q)
+      for (int dz : {-1, 1}) {
+        const int k0 = dz < 0 ? 1 : 0, k1 = dz < 0 ? nz : nz - 1;
+        for (int c0 = k0; c0 < k1; c0 += kChunk) {
+          std::vector<int> ids;
+          for (int k = c0; k < std::min(k1, c0 + kChunk); ++k) ids.push_back(new_instance(s));
+          fill(probs[q], ids, c0, dz);
+          pack_instances(ids, s);
+          for (size_t t = 0; t < ids.size(); ++t)
+            (dz < 0 ? Acur : Ccur)[q][c0 + (int)t] = Coupling{2, ids[t], nullptr};
+        }
+      }
+  }
   // H-inverse of the given planes of every problem, in place, with scratch
   // instances released right after; the inverses are final and get packed
   auto inverse_batch = [&](const std::vector<int>& planes) {
@@ -386,7 +438,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
         roles.push_back(tpool[b++]);
         done.push_back(probs[q].plane_inst[pl]);
       }
-    run_program(get_program("inv"), (int)nb, 2, roles, 0, {}, s);
+    run_program(get_program("inv"), (int)nb, 2, roles, 0, {}, lanes[0]);
     for (int t : tpool) release_instance(t);
     pack_instances(done, s);
   };
@@ -401,6 +453,21 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       }
     pack_instances(ids, s);
   };
+
+  // the previous level's new couplings still being formed on lane 1
+  struct Pending {
+    bool on = false;
+    std::vector<int> tmp;
+    std::vector<std::vector<Coupling>> An, Cn;
+  } pend;
+  auto join_pending = [&] {
+    if (!pend.on) return;
+    HIPCHK(hipStreamSynchronize(lanes[1].s));
+    for (int t : pend.tmp) release_instance(t);
+    pack_new_couplings(pend.An, pend.Cn);
+    pend = Pending{};
+  };
+  if (!ev_products) HIPCHK(hipEventCreateWithFlags(&ev_products, hipEventDisableTiming));
 
   std::vector<int> P(nz);
   for (int k = 0; k < nz; ++k) P[k] = k;
@@ -451,7 +518,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
       }
       probs[q].levels.push_back(Lq);
     }
-    if (lev == 0) {
+    if (lev == 0 && !fem27) {
       // D_j <- D_j - diag(a_j) Dinv_{j-1} diag(c_{j-1}) - diag(c_j) Dinv_{j+1} diag(a_{j+1})
       std::vector<int32_t> roles, roles2;
       std::vector<const double*> vecs, vecs2;
@@ -486,10 +553,11 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
           }
         }
       }
-      run_program(get_program("copy_schur"), (int)roles.size() / 3, 3, roles, 4, vecs, s);
-      run_program(get_program("copy_direct"), (int)roles2.size() / 2, 2, roles2, 2, vecs2, s);
+      run_program(get_program("copy_schur"), (int)roles.size() / 3, 3, roles, 4, vecs, lanes[0]);
+      run_program(get_program("copy_direct"), (int)roles2.size() / 2, 2, roles2, 2, vecs2, lanes[0]);
       pack_new_couplings(An, Cn);
     } else {
+      join_pending();  // this level's products read the couplings made by the previous one
       std::vector<int32_t> rXY, rS, rN;
       std::vector<int> tmp;
       for (int q = 0; q < np; ++q) {
@@ -520,12 +588,20 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
           }
         }
       }
-      run_program(get_program("mul_new"), (int)rXY.size() / 3, 3, rXY, 0, {}, s);
-      run_program(get_program("schur2"), (int)rS.size() / 5, 5, rS, 0, {}, s);
-      run_program(get_program("mul_neg"), (int)rN.size() / 3, 3, rN, 0, {}, s);
-      HIPCHK(hipStreamSynchronize(s));
-      for (int t : tmp) release_instance(t);
-      pack_new_couplings(An, Cn);
+      run_program(get_program("mul_new"), (int)rXY.size() / 3, 3, rXY, 0, {}, lanes[0]);
+      HIPCHK(hipEventRecord(ev_products, s));
+      run_program(get_program("schur2"), (int)rS.size() / 5, 5, rS, 0, {}, lanes[0]);
+      // the new couplings are needed only by the next level's products: they
+      // run on lane 1 while lane 0 goes on with the Schur updates and the
+      // next level's inverses; X and Y are released and the couplings packed
+      // when the next level joins them
+      ensure_lane(lanes[1], s);
+      HIPCHK(hipStreamWaitEvent(lanes[1].s, ev_products, 0));
+      run_program(get_program("mul_neg"), (int)rN.size() / 3, 3, rN, 0, {}, lanes[1]);
+      pend.on = true;
+      pend.tmp = tmp;
+      pend.An = An;
+      pend.Cn = Cn;
     }
     for (int q = 0; q < np; ++q)
       for (int j : L.K) {
@@ -535,6 +611,7 @@ void Handle::build_factors(hipStream_t s, const std::vector<int>& caps) {
     P = L.K;
     ++lev;
   }
+  join_pending();
   HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -738,9 +815,7 @@ void Handle::launch_phase(const PhaseJobs& pj, int ri, hipStream_t s) {
     a.nseg = (int)G.leaf_clusters.size();
     launch_mv<T>(a, s);
   };
-  if (bf16)
-    run(bf16s{});
-  else if (fp32)
+  if (fp32)
     run(float{});
   else
     run(double{});
@@ -789,13 +864,16 @@ void Handle::tune_apply(hipStream_t s) {
 }
 
 void Handle::matvec(int prob, const double* x, double* y, bool transpose, hipStream_t s) {
-  launch_stencil_mv(probs[prob].S, nx, ny, nz, transpose ? 1 : 0, x, y, s);
+  if (fem27)
+    launch_stencil27_mv(probs[prob].S, nx, ny, nz, transpose ? 1 : 0, x, y, s);
+  else
+    launch_stencil_mv(probs[prob].S, nx, ny, nz, transpose ? 1 : 0, x, y, s);
   HIPCHK(hipGetLastError());
 }
 
 // ------------------------------------------------------------ statistics
 double Handle::instance_bytes(const std::vector<int32_t>& rk) const {
-  const double esz = bf16 ? 2.0 : fp32 ? 4.0 : 8.0;
+  const double esz = fp32 ? 4.0 : 8.0;
   double b = 0.0;
   for (size_t l = 0; l < G.lf.size(); ++l) {
     const Leaf& L = G.lf[l];

@@ -24,7 +24,7 @@ int64_t dist2(const Cluster& a, const Cluster& b) {
 
 }  // namespace
 
-Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_work) {
+Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_work, bool diag9) {
   Geometry g;
   g.nx = nx;
   g.ny = ny;
@@ -105,9 +105,9 @@ Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_wor
     g.lf.push_back(L);
   }
 
-  // In-plane 5-point couplings inside an admissible low-rank leaf (possible
-  // only for large eta) would not be representable exactly at level 0:
-  // such leaves are kept dense.
+  // In-plane couplings (5-point, or 9-point with diag9) inside an admissible
+  // low-rank leaf (possible only for large eta) would not be representable
+  // exactly at level 0: such leaves are kept dense.
   {
     std::vector<int> pos(nx * ny);
     for (int i = 0; i < nx * ny; ++i) pos[g.perm[i]] = i;
@@ -129,8 +129,8 @@ Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_wor
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         int i = pos[x + nx * y];
-        const int dxs[4] = {-1, 1, 0, 0}, dys[4] = {0, 0, -1, 1};
-        for (int d = 0; d < 4; ++d) {
+        const int dxs[8] = {-1, 1, 0, 0, -1, 1, -1, 1}, dys[8] = {0, 0, -1, 1, -1, -1, 1, 1};
+        for (int d = 0; d < (diag9 ? 8 : 4); ++d) {
           int xx = x + dxs[d], yy = y + dys[d];
           if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) continue;
           int j = pos[xx + nx * yy];

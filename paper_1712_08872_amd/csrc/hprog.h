@@ -86,6 +86,15 @@ struct AccumArgs {
                                // sums, 2 the dense sums only
   unsigned long long* prof;    // optional cycle counters (null = off)
   double* flops;               // optional algorithmic flop counters by FlopClass (null = off)
+  int32_t bf16_products;       // 1: the matrix-core piece products take BF16 operands (rounded to
+                               // nearest even) with FP32 accumulation (FP32 factors, eps >= 1e-2)
+};
+
+// Level-0 conversion of a plane block: entry d < nd of the scatter map
+// (in-plane neighbour offset d of every row) takes stencil row row[d].
+struct L0Rows {
+  int32_t nd;
+  int32_t row[9];
 };
 
 // classes of the algorithmic flop counters of the accumulation kernels

@@ -34,7 +34,8 @@ void check_factor_blob(const acr_problem* p, const acr_options* o, const acr_fac
   if (o->precision == ACR_MIXED_BF16) throw AcrError(ACR_E_INVALID, "import supports FP64 and FP32 factors");
   const auto Pl = plane_lists(p->nz);
   const int top = (int)Pl.size() - 1;
-  const Geometry G = build_geometry(p->nx, p->ny, o->leaf_size, o->eta, o->dense_work);
+  const Geometry G = build_geometry(p->nx, p->ny, o->leaf_size, o->eta, o->dense_work,
+                                    p->kind == ACR_HELMHOLTZ_FEM27);
   std::map<std::tuple<int, int, int>, int> seen;
   for (int f = 0; f < blob->count; ++f) {
     const acr_factor& F = blob->factors[f];

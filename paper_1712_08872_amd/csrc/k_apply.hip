@@ -21,7 +21,6 @@
 #include <algorithm>
 #include <cstdint>
 
-#include "bf16.h"
 #include "hprog.h"
 
 namespace acr {
@@ -46,16 +45,7 @@ __device__ __forceinline__ void load4(const double* p, double* o) {
   o[3] = b.y;
 }
 
-__device__ __forceinline__ void load4(const bf16s* p, double* o) {
-  const uint2 v = *reinterpret_cast<const uint2*>(p);
-  o[0] = (double)bf16s{(uint16_t)(v.x & 0xffffu)};
-  o[1] = (double)bf16s{(uint16_t)(v.x >> 16)};
-  o[2] = (double)bf16s{(uint16_t)(v.y & 0xffffu)};
-  o[3] = (double)bf16s{(uint16_t)(v.y >> 16)};
-}
-
-// Four consecutive elements in the factor's own precision (16-byte loads
-// for FP32 and FP64, 8-byte loads for BF16).
+// Four consecutive elements in the factor's own precision (16-byte loads).
 template <typename T>
 __device__ __forceinline__ void load4raw(const T* p, T* o);
 template <>
@@ -65,14 +55,6 @@ __device__ __forceinline__ void load4raw<float>(const float* p, float* o) {
   o[1] = v.y;
   o[2] = v.z;
   o[3] = v.w;
-}
-template <>
-__device__ __forceinline__ void load4raw<bf16s>(const bf16s* p, bf16s* o) {
-  const uint2 v = *reinterpret_cast<const uint2*>(p);
-  o[0].b = (uint16_t)(v.x & 0xffffu);
-  o[1].b = (uint16_t)(v.x >> 16);
-  o[2].b = (uint16_t)(v.y & 0xffffu);
-  o[3].b = (uint16_t)(v.y >> 16);
 }
 template <>
 __device__ __forceinline__ void load4raw<double>(const double* p, double* o) {
@@ -101,7 +83,7 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
 }
 
 // Elements of a factor column per lane in the coefficient kernel: 4 for
-// FP64 factors, 8 for FP32 and BF16 ones.
+// FP64 factors, 8 for FP32 ones.
 template <typename T>
 struct Epl {
   static constexpr int value = sizeof(T) == 8 ? 4 : 8;
@@ -286,8 +268,8 @@ __device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* i
   return d;
 }
 
-// Columns per unit of the row kernel: two for FP32 and BF16 factors (32
-// bytes per lane per unit for FP32, as one column of FP64 factors).
+// Columns per unit of the row kernel: two for FP32 factors (32 bytes per
+// lane per unit, as one column of FP64 factors).
 template <typename T>
 struct RowCols {
   static constexpr int value = sizeof(T) == 8 ? 1 : 2;
@@ -598,23 +580,7 @@ void launch_mv(const MvArgs<T>& a, hipStream_t s) {
   }
 }
 
-// FP32 -> BF16, round to nearest even (the stored factors are finite).
-__global__ void to_bf16_kernel(const float* src, bf16s* dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t u = __float_as_uint(src[i]);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    dst[i].b = (uint16_t)(u >> 16);
-  }
-}
-
-void launch_to_bf16(const float* src, bf16s* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
-}
-
 template void launch_mv<double>(const MvArgs<double>&, hipStream_t);
-template void launch_mv<bf16s>(const MvArgs<bf16s>&, hipStream_t);
 template void launch_mv<float>(const MvArgs<float>&, hipStream_t);
 
 }  // namespace acr

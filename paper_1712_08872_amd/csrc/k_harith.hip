@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "hprog.h"
 
@@ -359,7 +360,7 @@ __device__ int onesided_jacobi(double* C, double* Z, int rows, int cols, int* sf
     if (prof && threadIdx.x == 0) atomicAdd(&prof[slot], (unsigned long long)(v)); \
   } while (0)
 
-template <typename T>
+template <typename T, bool BF = false>
 __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds& L, int32_t* flags,
                               unsigned long long* prof = nullptr) {
   const int tid = threadIdx.x;
@@ -627,6 +628,37 @@ struct Mfma16<double> {
   static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
 };
 
+// BF16 operands of the 16 x 16 x 16 matrix-core step (FP32 accumulation):
+// lane l supplies A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16],
+// e < 4; the accumulator layout is that of the FP32 16 x 16 x 4 step (row
+// 4 (l / 16) + r, column l % 16), as measured on gfx950.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short bf16_rne(float f) {  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// One 16 x 16 tile of Us Vs^T over `take` columns with BF16 operands, lane
+// layout as above.  Not inlined: inside the accumulate-only kernel its
+// conversions push the register allocation into heavy spilling.
+__device__ __attribute__((noinline)) Mfma16<float>::v4 bf16_outer_tile(const float* ui, const float* vj, bool ai,
+                                                                      bool bj, int take, int g) {
+  Mfma16<float>::v4 acc = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < take; k0 += 16) {
+    bf16x4_t a4, b4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + 4 * g + e;
+      const bool in = k < take;
+      a4[e] = bf16_rne((ai && in) ? ui[k] : 0.0f);
+      b4[e] = bf16_rne((bj && in) ? vj[k] : 0.0f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // Out[i][j] = sum_q P[q + i*ldp] * R[q + j*ldr] for i < mo, j < no (both
 // operands contiguous along q) on the matrix cores: 16 x 16 output tiles,
 // the operands read straight from memory (a lane takes 4 consecutive q of
@@ -634,7 +666,7 @@ struct Mfma16<double> {
 // tiles the chunks of a tile are split over the wavefronts and the partial
 // tiles added in a fixed order in LDS (`bP`, >= 4 x 256 elements).  Out is
 // LDS with leading dimension KC; mo, no <= KC.
-template <typename T>
+template <typename T, bool BF = false>
 __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int nq, int mo, int no,
                            typename CompT<T>::type* Out, typename CompT<T>::type* bP,
                            typename CompT<T>::type* bR, unsigned long long* prof) {
@@ -656,18 +688,38 @@ __device__ void tn_product(const T* P, int64_t ldp, const T* R, int64_t ldr, int
     const T* pa = P + (int64_t)i * ldp;
     const T* pb = R + (int64_t)j * ldr;
     V acc = {0, 0, 0, 0};
+    bool done = false;
+    if constexpr (sizeof(CT) == 4 && BF) {
+      {  // BF16 operands, one 16 x 16 x 16 step per chunk
 #pragma unroll 1
-    for (int c = part; c < nchunk; c += nparts) {
-      const int q = c * 16 + 4 * g;
-      CT av[4], bv[4];
+        for (int c = part; c < nchunk; c += nparts) {
+          const int q = c * 16 + 4 * g;
+          bf16x4_t a4, b4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const bool in = q + e < nq;
-        av[e] = (ai && in) ? (CT)pa[q + e] : (CT)0;
-        bv[e] = (bj && in) ? (CT)pb[q + e] : (CT)0;
+          for (int e = 0; e < 4; ++e) {
+            const bool in = q + e < nq;
+            a4[e] = bf16_rne((ai && in) ? (float)pa[q + e] : 0.0f);
+            b4[e] = bf16_rne((bj && in) ? (float)pb[q + e] : 0.0f);
+          }
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
+        }
+        done = true;
       }
+    }
+    if (!done) {
+#pragma unroll 1
+      for (int c = part; c < nchunk; c += nparts) {
+        const int q = c * 16 + 4 * g;
+        CT av[4], bv[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc = MF::step(av[e], bv[e], acc);
+        for (int e = 0; e < 4; ++e) {
+          const bool in = q + e < nq;
+          av[e] = (ai && in) ? (CT)pa[q + e] : (CT)0;
+          bv[e] = (bj && in) ? (CT)pb[q + e] : (CT)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = MF::step(av[e], bv[e], acc);
+      }
     }
     if (nparts == 1) {
 #pragma unroll
@@ -887,7 +939,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
 // of Us (target rows) and Vs (target columns), row-major ld KC.  The alpha
 // of the piece is folded into Us.  LDS buffers S0 (products), S1, S2
 // (staging) are used.
-template <typename T, typename LT>
+template <bool BF, typename T, typename LT>
 __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, const DLeaf& tc, int j0, int take,
                               T* Us, T* Vs, int K, LT& L) {
   using CT = typename CompT<T>::type;
@@ -935,8 +987,8 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       if (lam.fmt == 0) {
         for (int c0 = cA; c0 < cB; c0 += KC) {
           const int nc = imin(KC, cB - c0);
-          tn_product(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take, S0c, S1c,
-                     S2c, A.prof);
+          tn_product<T, BF>(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take,
+                            S0c, S1c, S2c, A.prof);
           FLOP(L, FC_PRODUCT, 2.0 * nq * nc * take);
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
@@ -950,7 +1002,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c, A.prof);
+        tn_product<T, BF>(Ul + (q0 - lam.r0), lr.ldu, vx, xr.ldv, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, S0c, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
                S1c, A.prof);
         FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (cB - cA)));
@@ -1005,7 +1057,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         if (kl == 0) continue;
         const T* Ul = lp;
         const T* Vl = lr.V;
-        tn_product(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c, A.prof);
+        tn_product<T, BF>(Vl + (q0 - lam.c0), lr.ldv, uy, yr.ldu, nq, kl, take, S0c, S1c, S2c, A.prof);
         nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, S0c, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
                S1c, A.prof);
         FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (rB - rA)));
@@ -1068,7 +1120,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
 // Dense target: C += Us Vs^T for `take` columns (C column-major m x n;
 // Us, Vs row-major with leading dimension KC): 16 x 16 tiles of C over the
 // wavefronts on the matrix cores.
-template <typename T, typename LT>
+template <bool BF, typename T, typename LT>
 __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs, int take, LT& L) {
   using CT = typename CompT<T>::type;
   using MF = Mfma16<CT>;
@@ -1084,13 +1136,20 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
     const int i = ti * 16 + l16, j = tj * 16 + l16;
     const bool ai = i < m, bj = j < n;
     V acc = {0, 0, 0, 0};
+    bool done = false;
+    if constexpr (sizeof(CT) == 4 && BF) {
+      acc = bf16_outer_tile(Us + (int64_t)i * KC, Vs + (int64_t)j * KC, ai, bj, take, g);
+      done = true;
+    }
+    if (!done) {
 #pragma unroll 4
-    for (int kk = 0; kk < nk; ++kk) {
-      const int k = 4 * kk + g;
-      const bool in = k < take;
-      const CT av = (ai && in) ? (CT)Us[(int64_t)i * KC + k] : (CT)0;
-      const CT bv = (bj && in) ? (CT)Vs[(int64_t)j * KC + k] : (CT)0;
-      acc = MF::step(av, bv, acc);
+      for (int kk = 0; kk < nk; ++kk) {
+        const int k = 4 * kk + g;
+        const bool in = k < take;
+        const CT av = (ai && in) ? (CT)Us[(int64_t)i * KC + k] : (CT)0;
+        const CT bv = (bj && in) ? (CT)Vs[(int64_t)j * KC + k] : (CT)0;
+        acc = MF::step(av, bv, acc);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1108,7 +1167,7 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
 // leading dimension tc.m).  Low-rank pieces are expanded `take` columns at a
 // time into the staging columns [0, take) of Us / Vs and added as outer
 // products.
-template <typename T, typename LT>
+template <bool BF, typename T, typename LT>
 __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
                              LT& L) {
   using CT = typename CompT<T>::type;
@@ -1162,9 +1221,9 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       const int w = piece_width(A, b, P);
       for (int j0 = 0; j0 < w; j0 += KC) {
         int take = imin(KC, w - j0);
-        piece_columns(A, b, P, tc, j0, take, Us, Vs, 0, L);
+        piece_columns<BF>(A, b, P, tc, j0, take, Us, Vs, 0, L);
         const long long to = clock64();
-        dense_add_outer(C, tc, Us, Vs, take, L);
+        dense_add_outer<BF>(C, tc, Us, Vs, take, L);
         PROF_ADD(PS_OUTER, clock64() - to);
         FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * take);
       }
@@ -1181,7 +1240,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
 // one block per CU (LDS): the whole register file, AGPRs included, is free
 #define ACCUM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(1, 1)))
 #endif
-template <typename T>
+template <typename T, bool BF>
 __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T> A) {
   __shared__ Lds L;
   const int tid = threadIdx.x;
@@ -1281,7 +1340,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
       while (j0 < w) {
         const int klim = imin(KC, kbase + ROUND);
         if (K >= klim) {
-          K = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
+          K = truncate_block<T, BF>(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
           if (K > KC - 8) {
             if (tid == 0) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
             K = KC - 8;
@@ -1301,7 +1360,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
           }
           __syncthreads();
         } else {
-          piece_columns(A, b, P, tc, j0, take, Us, Vs, K, L);
+          piece_columns<BF>(A, b, P, tc, j0, take, Us, Vs, K, L);
         }
         PROF_ADD(PS_PIECES_LR, clock64() - tp0);
         K += take;
@@ -1309,7 +1368,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
       }
     }
     if (dacc || tg.p1 > tg.p0 || !tg.beta) {
-      int k = truncate_block(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
+      int k = truncate_block<T, BF>(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
       int kw = imin(k, tc.cap);
       if (tid == 0) {
         if (k > tc.cap) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
@@ -1346,7 +1405,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
 // sum of every small low-rank target that is summed densely (same decision
 // as the truncating kernel, which then compresses it).  No truncation
 // workspace: a small LDS footprint, more resident blocks.
-template <typename T>
+template <typename T, bool BF>
 __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumArgs<T> A) {
   __shared__ LdsPiece<typename CompT<T>::type> L;
   __shared__ int wsum;
@@ -1375,7 +1434,7 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
       if (!tg.beta)
         for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
       __syncthreads();
-      dense_pieces(A, b, tg, tc, C, Us, Vs, L);
+      dense_pieces<BF>(A, b, tg, tc, C, Us, Vs, L);
       PROF_ADD(PS_DENSE, clock64() - t_item);
       continue;
     }
@@ -1396,7 +1455,7 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
     }
     FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * k0);
     __syncthreads();
-    dense_pieces(A, b, tg, tc, D, Us, Vs, L);
+    dense_pieces<BF>(A, b, tg, tc, D, Us, Vs, L);
     PROF_ADD(PS_DACC, clock64() - t_item);
   }
   if (tid == 0 && A.flops)
@@ -1404,13 +1463,27 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
 }
 
 // ------------------------------------------------------------ launchers
+// BF16 piece products are a separate build of the FP32 kernels, so that the
+// FP32 build keeps its registers (the BF16 branches would make it spill).
 template <typename T>
 void launch_accum(const AccumArgs<T>& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(accum_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.bf16_products) {
+      hipLaunchKernelGGL((accum_kernel<T, true>), dim3(grid), dim3(TPB), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((accum_kernel<T, false>), dim3(grid), dim3(TPB), 0, s, a);
 }
 template <typename T>
 void launch_accum_dense(const AccumArgs<T>& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(accum_dense_kernel<T>, dim3(grid), dim3(TPB), 0, s, a);
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.bf16_products) {
+      hipLaunchKernelGGL((accum_dense_kernel<T, true>), dim3(grid), dim3(TPB), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((accum_dense_kernel<T, false>), dim3(grid), dim3(TPB), 0, s, a);
 }
 template void launch_accum_dense<double>(const AccumArgs<double>&, int, hipStream_t);
 template void launch_accum_dense<float>(const AccumArgs<float>&, int, hipStream_t);
@@ -1501,16 +1574,15 @@ __global__ __launch_bounds__(TPB) void leaf_inverse_kernel(T* const* inst_base, 
 // (row i, column of neighbour d) or -1; d = centre, x-1, x+1, y-1, y+1.
 template <typename T>
 __global__ void level0_kernel(T* const* inst_base, const int32_t* insts, int nplanes, int plane0, const double* S,
-                              int64_t N, int B, const int32_t* perm, const int64_t* map) {
+                              int64_t N, int B, const int32_t* perm, const int64_t* map, L0Rows rows) {
   const int64_t total = (int64_t)nplanes * B;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
     int k = (int)(g / B), i = (int)(g - (int64_t)k * B);
     int64_t p = (int64_t)(plane0 + k) * B + perm[i];
     T* base = inst_base[insts[k]];
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
+    for (int d = 0; d < rows.nd; ++d) {
       int64_t o = map[(int64_t)d * B + i];
-      if (o >= 0) base[o] = (T)S[(int64_t)d * N + p];
+      if (o >= 0) base[o] = (T)S[(int64_t)rows.row[d] * N + p];
     }
   }
 }
@@ -1535,11 +1607,12 @@ void launch_leaf_inverse(T* const* base, const int32_t* insts, int stride, int n
 }
 template <typename T>
 void launch_level0(T* const* base, const int32_t* insts, int nplanes, int plane0, const double* S, int64_t N, int B,
-                   const int32_t* perm, const int64_t* map, hipStream_t s) {
+                   const int32_t* perm, const int64_t* map, const L0Rows& rows, hipStream_t s) {
   int64_t total = (int64_t)nplanes * B;
   int grid = (int)((total + 255) / 256);
   if (grid > 65535) grid = 65535;
-  hipLaunchKernelGGL(level0_kernel<T>, dim3(grid), dim3(256), 0, s, base, insts, nplanes, plane0, S, N, B, perm, map);
+  hipLaunchKernelGGL(level0_kernel<T>, dim3(grid), dim3(256), 0, s, base, insts, nplanes, plane0, S, N, B, perm, map,
+                     rows);
 }
 void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
                       hipStream_t s) {
@@ -1552,9 +1625,9 @@ template void launch_leaf_inverse<double>(double* const*, const int32_t*, int, i
                                           hipStream_t);
 template void launch_leaf_inverse<float>(float* const*, const int32_t*, int, int, int64_t, int, int32_t*, hipStream_t);
 template void launch_level0<double>(double* const*, const int32_t*, int, int, const double*, int64_t, int,
-                                    const int32_t*, const int64_t*, hipStream_t);
+                                    const int32_t*, const int64_t*, const L0Rows&, hipStream_t);
 template void launch_level0<float>(float* const*, const int32_t*, int, int, const double*, int64_t, int,
-                                   const int32_t*, const int64_t*, hipStream_t);
+                                   const int32_t*, const int64_t*, const L0Rows&, hipStream_t);
 #endif
 
 }  // namespace acr

@@ -93,6 +93,97 @@ __global__ void stencil_mv_kernel(const double* __restrict__ S, int nx, int ny, 
   }
 }
 
+// ---------------------------------------------------------------- 27-point
+// Trilinear (Q1) finite elements for -Lap u - omega^2 / c^2 u (Sec. 8, eq.
+// HelmVarVel; the 27-point scheme on hexahedra).  Row p is the sum over the
+// 8 elements around node p of K_e - M_e: the Q1 stiffness of -Lap, products
+// of the 1D element matrices k = [[1, -1], [-1, 1]] / h and
+// m = [[2, 1], [1, 2]] h / 6, minus the mass weighted by omega^2 / c^2 with
+// the 2 x 2 x 2 Gauss rule, c interpolated trilinearly from the element's
+// node values.  S row m = (dx+1) + 3 (dy+1) + 9 (dz+1) holds the coupling to
+// the neighbour at offset (dx, dy, dz); couplings to boundary nodes are 0.
+__global__ void assemble27_kernel(int nx, int ny, int nz, const double* c, double omega, double* S) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1), hz = 1.0 / (nz + 1);
+  const double hh[3] = {hx, hy, hz};
+  const int sx = nx + 2, sy = ny + 2;
+  const double gp[2] = {0.5 - 0.5 / sqrt(3.0), 0.5 + 0.5 / sqrt(3.0)};
+  const double wq = hx * hy * hz / 8.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+    const int I = i + 1, J = j + 1, K = k + 1;  // node-grid coordinates
+    double acc[27];
+#pragma unroll
+    for (int m = 0; m < 27; ++m) acc[m] = 0.0;
+    for (int e = 0; e < 8; ++e) {
+      // element with first node (ex, ey, ez); p is its local node a
+      const int ax = e & 1, ay = (e >> 1) & 1, az = e >> 2;
+      const int ex = I - ax, ey = J - ay, ez = K - az;
+      const int a = ax + 2 * ay + 4 * az;
+      double ce[8], mab[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        ce[b] = c[(ex + (b & 1)) + (int64_t)sx * ((ey + ((b >> 1) & 1)) + (int64_t)sy * (ez + (b >> 2)))];
+        mab[b] = 0.0;
+      }
+      for (int qz = 0; qz < 2; ++qz)
+        for (int qy = 0; qy < 2; ++qy)
+          for (int qx = 0; qx < 2; ++qx) {
+            const double xi[3] = {gp[qx], gp[qy], gp[qz]};
+            double phi[8], cq = 0.0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+              const double fx = (b & 1) ? xi[0] : 1.0 - xi[0];
+              const double fy = ((b >> 1) & 1) ? xi[1] : 1.0 - xi[1];
+              const double fz = (b >> 2) ? xi[2] : 1.0 - xi[2];
+              phi[b] = fx * fy * fz;
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) cq += phi[b] * ce[b];
+            const double kq = omega * omega / (cq * cq) * wq;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) mab[b] += kq * (phi[a] * phi[b]);
+          }
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        const int dx = bx - ax, dy = by - ay, dz = bz - az;
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
+        const int aa[3] = {ax, ay, az}, bb[3] = {bx, by, bz};
+        double kd[3], md[3];
+        for (int d = 0; d < 3; ++d) {
+          kd[d] = (aa[d] == bb[d] ? 1.0 : -1.0) / hh[d];
+          md[d] = (aa[d] == bb[d] ? 2.0 : 1.0) * hh[d] / 6.0;
+        }
+        const double kab = kd[0] * md[1] * md[2] + md[0] * kd[1] * md[2] + md[0] * md[1] * kd[2];
+        acc[(dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)] += kab - mab[b];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 27; ++m) S[(int64_t)m * N + p] = acc[m];
+  }
+}
+
+// y = A x (transpose = 0) or A^T x (transpose = 1) with a 27-point stencil
+// (row m = (dx+1) + 3 (dy+1) + 9 (dz+1)); the transpose reads the
+// neighbour's coupling of the opposite offset, row 26 - m.
+__global__ void stencil27_mv_kernel(const double* __restrict__ S, int nx, int ny, int nz, int transpose,
+                                    const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));
+    double s = 0.0;
+    for (int m = 0; m < 27; ++m) {
+      const int dx = m % 3 - 1, dy = (m / 3) % 3 - 1, dz = m / 9 - 1;
+      if (i + dx < 0 || i + dx >= nx || j + dy < 0 || j + dy >= ny || k + dz < 0 || k + dz >= nz) continue;
+      const int64_t q = p + dx + (int64_t)nx * (dy + (int64_t)ny * dz);
+      s += (transpose ? S[(int64_t)(26 - m) * N + q] : S[(int64_t)m * N + p]) * x[q];
+    }
+    y[p] = s;
+  }
+}
+
 // dJ/dkappa_m = -sum over faces (m,o) of dkf/dkm / h^2 *
 //   ( [m interior] lam_m (u_m - u_o) + [o interior] lam_o (u_o - u_m) ),
 // u = lam = 0 on the boundary; dkf/dkm = 2 kappa_o^2 / (kappa_m + kappa_o)^2.
@@ -265,6 +356,14 @@ void launch_assemble(int kind, int nx, int ny, int nz, const double* kappa, doub
 void launch_stencil_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t s) {
   int64_t N = (int64_t)nx * ny * nz;
   hipLaunchKernelGGL(stencil_mv_kernel, dim3(grid_for(N)), dim3(256), 0, s, S, nx, ny, nz, tr, x, y);
+}
+void launch_assemble27(int nx, int ny, int nz, const double* c, double omega, double* S, hipStream_t s) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(assemble27_kernel, dim3(grid_for(N)), dim3(256), 0, s, nx, ny, nz, c, omega, S);
+}
+void launch_stencil27_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t s) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(stencil27_mv_kernel, dim3(grid_for(N)), dim3(256), 0, s, S, nx, ny, nz, tr, x, y);
 }
 void launch_grad_kappa(int nx, int ny, int nz, const double* kappa, const double* u, const double* lam, double* g,
                        hipStream_t s) {

@@ -59,13 +59,21 @@ void Handle::dfree(void* p) {
 }
 
 Handle::~Handle() {
-  if (s2) {
-    (void)hipStreamSynchronize(s2);
-    (void)hipStreamDestroy(s2);
+  for (int l = 0; l < 2; ++l) {
+    Lane& ln = lanes[l];
+    if (ln.s2) {
+      (void)hipStreamSynchronize(ln.s2);
+      (void)hipStreamDestroy(ln.s2);
+    }
+    if (l == 1 && ln.s) {  // lane 0's main stream is the caller's
+      (void)hipStreamSynchronize(ln.s);
+      (void)hipStreamDestroy(ln.s);
+    }
+    if (ln.fork) (void)hipEventDestroy(ln.fork);
+    if (ln.join) (void)hipEventDestroy(ln.join);
   }
-  if (ev_fork) (void)hipEventDestroy(ev_fork);
-  if (ev_join) (void)hipEventDestroy(ev_join);
   if (kbuf.hres) (void)hipHostFree(kbuf.hres);
+  if (ev_products) (void)hipEventDestroy(ev_products);
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   for (auto& o : owned) {
     if (opt.free)
@@ -247,36 +255,11 @@ void Handle::pack_instances(const std::vector<int>& ids, hipStream_t s) {
   table_dirty = true;
 }
 
-// ACR_MIXED_BF16: every stored (packed, FP32) factor is replaced by its
-// BF16 rounding, same layout and offsets in elements.
-void Handle::round_factors_bf16(hipStream_t s) {
-  HIPCHK(hipStreamSynchronize(s));
-  const size_t nl = G.lf.size();
-  for (Instance& I : inst) {
-    if (!I.live) continue;
-    if (!I.packed) throw AcrError(ACR_E_DEVICE, "internal: unpacked factor at the end of setup");
-    const int64_t elems = (int64_t)(I.packed_bytes / 4.0);
-    const size_t data = round_up((size_t)elems * 2, 256);
-    const size_t rbytes = round_up(nl * sizeof(int32_t), 256);
-    char* nb = (char*)dmalloc(data + rbytes + nl * sizeof(int64_t));
-    launch_to_bf16((const float*)I.base, (bf16s*)nb, elems, s);
-    HIPCHK(hipMemcpyAsync(nb + data, I.rank, nl * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(nb + data + rbytes, I.off, nl * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));  // the FP32 copy is read until here
-    dfree(I.buf);
-    I.buf = nb;
-    I.base = nb;
-    I.rank = (int32_t*)(nb + data);
-    I.off = (int64_t*)(nb + data + rbytes);
-    I.packed_bytes = (double)elems * 2.0;
-  }
-  HIPCHK(hipGetLastError());
-  table_dirty = true;
-}
-
 void Handle::sync_tables() {
   if (!table_dirty) return;
   if ((int)inst.size() > inst_table_cap) {
+    if (lanes[1].s) HIPCHK(hipStreamSynchronize(lanes[1].s));  // it may read the old tables
+    if (lanes[1].s2) HIPCHK(hipStreamSynchronize(lanes[1].s2));
     if (d_inst_base) dfree(d_inst_base);
     if (d_inst_rank) dfree(d_inst_rank);
     if (d_inst_off) dfree(d_inst_off);
@@ -322,8 +305,25 @@ void Handle::upload_program(Program& p) {
   p.d_doff = upload(p.doff);
 }
 
+// Streams, events and accumulation scratch of a lane (created on first use;
+// every stream of the library has the default priority).
+void Handle::ensure_lane(Lane& ln, hipStream_t main) {
+  if (&ln == &lanes[0]) {
+    ln.s = main;
+  } else if (!ln.s) {
+    HIPCHK(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
+  }
+  if (!ln.s2) {
+    HIPCHK(hipStreamCreateWithFlags(&ln.s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ln.join, hipEventDisableTiming));
+  }
+  if (!ln.scratch) ln.scratch = dmalloc((size_t)2 * scratch_slots * scratch_stride * (fp32 ? 4 : 8));
+}
+
 template <typename T>
-void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, hipStream_t s) {
+void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, Lane& ln) {
+  const hipStream_t s = ln.s, s2 = ln.s2;
   // batch chunks whose dense accumulators fit the buffer limit
   constexpr size_t kDbufMax = size_t(4) << 30;
   int chunk = nbatch;
@@ -331,17 +331,12 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
     const size_t per = (size_t)st.dstride * sizeof(T);
     chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nbatch, (int64_t)(kDbufMax / per)));
     const size_t need = per * (size_t)chunk;
-    if (need > dbuf_bytes) {
-      if (dbuf) dfree(dbuf);
-      dbuf = dmalloc(need);
-      dbuf_bytes = need;
+    if (need > ln.dbuf_bytes) {
+      HIPCHK(hipStreamSynchronize(s));  // the lane's previous steps are done with the buffer
+      if (ln.dbuf) dfree(ln.dbuf);
+      ln.dbuf = dmalloc(need);
+      ln.dbuf_bytes = need;
     }
-  }
-  if (!s2) {
-    // default priority, like every stream of the library
-    HIPCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
   }
   for (int b0 = 0; b0 < nbatch; b0 += chunk) {
     const int nb = std::min(chunk, nbatch - b0);
@@ -355,20 +350,21 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
     a.nbatch = nb;
     a.nroles = nroles;
     a.nvroles = nvroles;
-    a.role_inst = d_roles + (size_t)b0 * nroles;
-    a.vec_ptr = nvroles > 0 ? d_vecs + (size_t)b0 * nvroles : nullptr;
+    a.role_inst = ln.d_roles + (size_t)b0 * nroles;
+    a.vec_ptr = nvroles > 0 ? ln.d_vecs + (size_t)b0 * nvroles : nullptr;
     a.inst_base = (T* const*)d_inst_base;
     a.inst_rank = d_inst_rank;
     a.inst_off = d_inst_off;
-    a.scratch = (T*)scratch;
+    a.scratch = (T*)ln.scratch;
     a.scratch_stride = scratch_stride;
     a.eps = opt.eps;
     a.flags = d_flags;
-    a.dbuf = (T*)dbuf;
+    a.dbuf = (T*)ln.dbuf;
     a.doff = P.d_doff;
     a.dstride = st.dstride;
     a.prof = d_prof;
     a.flops = d_flops;
+    a.bf16_products = bf16 ? 1 : 0;
     const int64_t items = (int64_t)nb * st.nt;
     const int grid = (int)std::min<int64_t>(items, scratch_slots);
     auto timed = [&](hipStream_t q, auto&& launch, const char* tag_suffix) {
@@ -394,9 +390,9 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
     // the next step.
     AccumArgs<T> a1 = a;
     a1.mode = 1;
-    a1.scratch = (T*)scratch + (int64_t)scratch_slots * scratch_stride;
-    HIPCHK(hipEventRecord(ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(s2, ev_fork, 0));
+    a1.scratch = (T*)ln.scratch + (int64_t)scratch_slots * scratch_stride;
+    HIPCHK(hipEventRecord(ln.fork, s));
+    HIPCHK(hipStreamWaitEvent(s2, ln.fork, 0));
     timed(s2, [&] {
       if (kc == 38)
         kc38::launch_accum<T>(a1, grid, s2);
@@ -424,12 +420,12 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
       ++accum_launches;
     }
     ++accum_launches;
-    HIPCHK(hipEventRecord(ev_join, s2));
-    HIPCHK(hipStreamWaitEvent(s, ev_join, 0));
+    HIPCHK(hipEventRecord(ln.join, s2));
+    HIPCHK(hipStreamWaitEvent(s, ln.join, 0));
   }
 }
-template void Handle::run_accum_step<float>(Program&, const Step&, int, int, int, hipStream_t);
-template void Handle::run_accum_step<double>(Program&, const Step&, int, int, int, hipStream_t);
+template void Handle::run_accum_step<float>(Program&, const Step&, int, int, int, Lane&);
+template void Handle::run_accum_step<double>(Program&, const Step&, int, int, int, Lane&);
 
 Program& Handle::get_program(const std::string& key) {
   auto it = prog.find(key);
@@ -469,25 +465,26 @@ Program& Handle::get_program(const std::string& key) {
 }
 
 void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
-                         const std::vector<const double*>& vecs, hipStream_t s) {
+                         const std::vector<const double*>& vecs, Lane& ln) {
   if (nbatch <= 0) return;
+  const hipStream_t s = ln.s;
   sync_tables();
-  // role and vector tables of this run (synchronous copies: the host
-  // vectors are rewritten by the next call)
-  if ((int)roles.size() > roles_cap) {
-    if (d_roles) dfree(d_roles);
-    roles_cap = std::max<int>(1024, (int)roles.size() * 2);
-    d_roles = dnew<int32_t>(roles_cap);
-  }
+  // role and vector tables of this run (synchronous copies after the lane's
+  // previous work: the host vectors are rewritten by the next call)
   HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipMemcpy(d_roles, roles.data(), roles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if ((int)roles.size() > ln.roles_cap) {
+    if (ln.d_roles) dfree(ln.d_roles);
+    ln.roles_cap = std::max<int>(1024, (int)roles.size() * 2);
+    ln.d_roles = dnew<int32_t>(ln.roles_cap);
+  }
+  HIPCHK(hipMemcpy(ln.d_roles, roles.data(), roles.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   if (!vecs.empty()) {
-    if ((int)vecs.size() > vecs_cap) {
-      if (d_vecs) dfree((void*)d_vecs);
-      vecs_cap = std::max<int>(1024, (int)vecs.size() * 2);
-      d_vecs = dnew<const double*>(vecs_cap);
+    if ((int)vecs.size() > ln.vecs_cap) {
+      if (ln.d_vecs) dfree((void*)ln.d_vecs);
+      ln.vecs_cap = std::max<int>(1024, (int)vecs.size() * 2);
+      ln.d_vecs = dnew<const double*>(ln.vecs_cap);
     }
-    HIPCHK(hipMemcpy((void*)d_vecs, vecs.data(), vecs.size() * sizeof(double*), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy((void*)ln.d_vecs, vecs.data(), vecs.size() * sizeof(double*), hipMemcpyHostToDevice));
   }
   for (size_t si = 0; si < P.steps.size(); ++si) {
     const Step& st = P.steps[si];
@@ -495,15 +492,16 @@ void Handle::run_program(Program& P, int nbatch, int nroles, const std::vector<i
       const Leaf& L = G.lf[st.leaf];
       leaf_inverse_flops += 2.0 * L.m * L.m * L.m * nbatch;  // LU and inverse of an m x m leaf
       if (fp32)
-        launch_leaf_inverse<float>((float* const*)d_inst_base, d_roles, nroles, nbatch, L.off, L.m, d_flags, s);
+        launch_leaf_inverse<float>((float* const*)d_inst_base, ln.d_roles, nroles, nbatch, L.off, L.m, d_flags, s);
       else
-        launch_leaf_inverse<double>((double* const*)d_inst_base, d_roles, nroles, nbatch, L.off, L.m, d_flags, s);
+        launch_leaf_inverse<double>((double* const*)d_inst_base, ln.d_roles, nroles, nbatch, L.off, L.m, d_flags,
+                                    s);
       continue;
     }
     if (fp32)
-      run_accum_step<float>(P, st, nbatch, nroles, nvroles, s);
+      run_accum_step<float>(P, st, nbatch, nroles, nvroles, ln);
     else
-      run_accum_step<double>(P, st, nbatch, nroles, nvroles, s);
+      run_accum_step<double>(P, st, nbatch, nroles, nvroles, ln);
   }
   HIPCHK(hipGetLastError());
 }

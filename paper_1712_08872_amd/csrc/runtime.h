@@ -11,7 +11,6 @@
 
 #include "../../include/acr.h"
 #include "geometry.h"
-#include "bf16.h"
 #include "hprog.h"
 #include "program.h"
 
@@ -44,17 +43,18 @@ void launch_leaf_inverse(T* const*, const int32_t*, int stride, int ninst, int64
                          hipStream_t);
 template <typename T>
 void launch_level0(T* const*, const int32_t*, int nplanes, int plane0, const double* S, int64_t N, int B,
-                   const int32_t* perm, const int64_t* map, hipStream_t);
+                   const int32_t* perm, const int64_t* map, const L0Rows& rows, hipStream_t);
 void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* perm, double* outA, double* outC,
                       hipStream_t);
 template <typename T> void launch_mv(const MvArgs<T>&, hipStream_t);
-void launch_to_bf16(const float* src, bf16s* dst, int64_t n, hipStream_t s);
 template <typename T>
 void launch_pack(const T* src, const int32_t* rank, const DLeaf* leaves, int nleaf, T* dst, const int64_t* off,
                  hipStream_t);
 void launch_assemble(int kind, int nx, int ny, int nz, const double* kappa, double ba, double bph, const double* c,
                      double omega, double* S, hipStream_t);
 void launch_stencil_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t);
+void launch_assemble27(int nx, int ny, int nz, const double* c, double omega, double* S, hipStream_t);
+void launch_stencil27_mv(const double* S, int nx, int ny, int nz, int tr, const double* x, double* y, hipStream_t);
 void launch_grad_kappa(int nx, int ny, int nz, const double* kappa, const double* u, const double* lam, double* g,
                        hipStream_t);
 void launch_to_horder(const double* n, double* h, const int32_t* perm, int B, int64_t N, hipStream_t);
@@ -130,7 +130,7 @@ struct PhaseJobs {           // device job array of one apply phase
 struct Prob {
   int kind = 0;
   double beta_amp = 0, beta_phase = 0, omega = 0;
-  double* S = nullptr;       // 7 * N assembled stencil
+  double* S = nullptr;       // nst() * N assembled stencil
   double* kappa = nullptr;   // node-grid copy (Poisson / convection-diffusion)
   double *zA = nullptr, *zC = nullptr;  // H-ordered level-0 z-couplings
   std::vector<Level> levels;
@@ -145,7 +145,9 @@ struct Handle {
   int64_t N = 0;               // unknowns of one problem
   acr_options opt{};
   bool fp32 = false;  // FP32 factors during setup (ACR_MIXED_FP32 and ACR_MIXED_BF16)
-  bool bf16 = false;  // stored factors rounded to BF16 at the end of setup
+  bool fem27 = false; // 27-point operator: 9-point plane couplings held as H-matrices from level 0
+  int nst() const { return fem27 ? 27 : 7; }  // stencil rows per unknown
+  bool bf16 = false;  // ACR_MIXED_BF16: piece products on BF16 matrix cores (FP32 factors)
   std::vector<double> level_secs;  // setup wall time per CR level (last build)
   std::vector<Prob> probs;
   // allocator
@@ -187,21 +189,34 @@ struct Handle {
   int new_instance(hipStream_t s);
   void release_instance(int id);
   void pack_instances(const std::vector<int>& ids, hipStream_t s);
-  void round_factors_bf16(hipStream_t s);
   void sync_tables();
   // programs
   std::map<std::string, Program> prog;
   Program& get_program(const std::string& key);
   void upload_program(Program& p);
-  // scratch for accumulation
-  void* scratch = nullptr;
+  // A lane runs one H-arithmetic program at a time: a main stream (lane 0:
+  // the caller's), a second stream for the targets of a step that do not
+  // need its first phase, the accumulation scratch (one region of
+  // scratch_slots slots per stream), the dense accumulators of two-phase
+  // steps and the role tables.  Lane 1 runs a level's new couplings while
+  // lane 0 goes on with the Schur updates and the next level's inverses.
+  struct Lane {
+    hipStream_t s = nullptr, s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void* scratch = nullptr;
+    void* dbuf = nullptr;      // dense accumulators (a chunk of batch items)
+    size_t dbuf_bytes = 0;
+    int32_t* d_roles = nullptr;
+    int roles_cap = 0;
+    const double** d_vecs = nullptr;
+    int vecs_cap = 0;
+  };
+  Lane lanes[2];
   int64_t scratch_stride = 0;
   int scratch_slots = 0;
   int kc = 64;                 // round width of the accumulation kernel in use
-  hipStream_t s2 = nullptr;    // second stream of a step (targets independent of the first phase)
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  void* dbuf = nullptr;        // dense accumulators of a two-phase step (chunk of batch items)
-  size_t dbuf_bytes = 0;
+  void ensure_lane(Lane& ln, hipStream_t main);
+  hipEvent_t ev_products = nullptr;  // a level's first products done (lane 1 may start)
   int32_t* d_flags = nullptr;
   unsigned long long* d_prof = nullptr;  // optional kernel cycle counters (ACR_PROFILE=1)
   double* d_flops = nullptr;             // optional algorithmic flop counters (ACR_KERNEL_TIMING=1):
@@ -218,10 +233,6 @@ struct Handle {
   std::vector<LaunchTag> ev_tag;  // one per timed launch (ACR_KERNEL_TIMING=1)
   int cur_level = -1;
   int accum_launches = 0, dense_launches = 0;
-  int32_t* d_roles = nullptr;
-  int roles_cap = 0;
-  const double** d_vecs = nullptr;
-  int vecs_cap = 0;
   // apply workspace (all problems, plane vectors concatenated by problem)
   double *g = nullptr, *w = nullptr, *z = nullptr, *coef = nullptr;
   int max_jobs = 0;
@@ -245,9 +256,9 @@ struct Handle {
   void build_factors(hipStream_t s, const std::vector<int>& caps);
   void free_factors();
   void run_program(Program& P, int nbatch, int nroles, const std::vector<int32_t>& roles, int nvroles,
-                   const std::vector<const double*>& vecs, hipStream_t s);
+                   const std::vector<const double*>& vecs, Lane& ln);
   template <typename T>
-  void run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, hipStream_t s);
+  void run_accum_step(Program& P, const Step& st, int nbatch, int nroles, int nvroles, Lane& ln);
   void build_apply_jobs();
   void launch_phase(const PhaseJobs& pj, int ri, hipStream_t s);
   void tune_apply(hipStream_t s);
@@ -287,4 +298,16 @@ struct acr_handle {
   std::vector<std::pair<int, int>> where;  // problem -> (group, index in group)
   std::vector<int64_t> off, grid_off;      // vector / node-grid offsets per problem
   int64_t total = 0, grid_total = 0;
+  // several groups: one stream per group (default priority), so that the
+  // groups' setups and applies run concurrently, and the events that fork
+  // from and join to the caller's stream
+  std::vector<hipStream_t> gstream;
+  std::vector<hipEvent_t> gdone;
+  hipEvent_t fork = nullptr;
+  ~acr_handle() {
+    groups.clear();  // the groups' memory first (their work is complete)
+    for (hipStream_t s : gstream) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : gdone) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
 };

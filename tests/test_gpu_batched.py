@@ -1,7 +1,8 @@
 """Batched independent problems: one handle, problems grouped by shape, every
-setup step and apply phase batched over all planes of a group.  Each
-problem's preconditioner must equal the one built for it alone (bitwise: the
-same kernels perform the same arithmetic in the same order)."""
+setup step and apply phase batched over all planes of a group, the groups
+running concurrently (a host thread and a stream each).  Each problem's
+preconditioner must equal the one built for it alone (bitwise: the same
+kernels perform the same arithmetic in the same order)."""
 import numpy as np
 import pytest
 
@@ -56,3 +57,20 @@ def test_batched_krylov_solves_every_problem():
         assert float(rel) <= 1e-10
     st = acr.acr_stats(hb)
     assert st["factors"] > 0 and st["rank_overflow"] == 0
+
+
+def test_concurrent_shape_groups_equal_serial(monkeypatch):
+    """Shape groups set up concurrently (a host thread and a stream each)
+    give the factors of the groups set up one after another, and the
+    applies forked over the groups' streams equal the serial ones."""
+    specs = [(13, 121, acr.POISSON_HARMONIC), (9, 122, acr.CONVDIFF_UPWIND), (11, 123, acr.POISSON_HARMONIC),
+             (13, 124, acr.CONVDIFF_UPWIND)]
+    probs = [_problem(*s) for s in specs]
+    hc = acr.acr_setup_batched(probs, eps=1e-5, precision=acr.MIXED_FP32)
+    monkeypatch.setenv("ACR_SERIAL_GROUPS", "1")
+    hs = acr.acr_setup_batched(probs, eps=1e-5, precision=acr.MIXED_FP32)
+    r = torch.from_numpy(synth.rhs_uniform(hc.total, 11)).cuda()
+    assert torch.equal(acr.acr_apply(hc, r), acr.acr_apply(hs, r))
+    assert torch.equal(acr.acr_apply_T(hc, r), acr.acr_apply_T(hs, r))
+    sc, ss = acr.acr_stats(hc), acr.acr_stats(hs)
+    assert sc["bytes_factors"] == ss["bytes_factors"] and sc["max_rank"] == ss["max_rank"]

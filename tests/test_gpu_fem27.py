@@ -1,0 +1,119 @@
+"""The 27-point trilinear finite-element Helmholtz problem of Sec. 8 (eq.
+HelmVarVel: waveguide velocity, Dirichlet boundary) through the C ABI,
+against the oracle: the assembled stencil, the 27-point matrix-vector
+product and its transpose, the preconditioner and its exact transpose
+(within 10 eps of the oracle's H-matrix cyclic reduction, whose level-0
+couplings are 9-point H-matrices so that level 0 runs the formatted
+products), and GMRES against a sparse direct solve.
+
+The cases are chosen so that the oracle's preconditioner is itself within
+eps-scale of the exact inverse.  The indefinite operator can make a reduced
+plane system nearly singular, which amplifies every eps-truncation; there
+two valid truncations (the GPU's and the oracle's) cannot agree to 10 eps,
+and the last test checks that case against the exact solve instead."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import fem27, hacr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1712_08872_amd as acr  # noqa: E402
+
+CASES = {
+    # name: (nx, ny, nz, frequency f (omega = 2 pi f), eps, eta, leaf)
+    "waveguide15": (15, 15, 15, 2.0, 1e-6, 1.0, 16),
+    "ragged13x11x9": (13, 11, 9, 1.5, 1e-5, 2.0, 16),
+    "waveguide19x17x8_e4": (19, 17, 8, 1.5, 1e-4, 1.0, 32),
+}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    nx, ny, nz, fr, eps, eta, leaf = CASES[request.param]
+    print(f"\n[fem27 case {request.param}] {nx}x{ny}x{nz} f={fr} eps={eps} eta={eta} leaf={leaf}", flush=True)
+    c = fem27.waveguide_velocity(nx, ny, nz)
+    om = 2.0 * np.pi * fr
+    S = fem27.stencil27(nx, ny, nz, c, om)
+    H = hacr.HACR(S, nx, ny, nz, eps=eps, eta=eta, leaf=leaf)
+    h = acr.acr_setup(nx, ny, nz, acr.HELMHOLTZ_FEM27, c=_dev(c), omega=om, eps=eps, eta=eta, leaf_size=leaf)
+    return dict(n=(nx, ny, nz), eps=eps, S=S, H=H, h=h, A=fem27.to_sparse27(S, nx, ny, nz))
+
+
+def test_assembly_matches_oracle(case):
+    Sg = acr.acr_get_stencil(case["h"]).cpu().numpy().reshape(27, -1)
+    np.testing.assert_allclose(Sg, case["S"], rtol=1e-13, atol=1e-13 * np.abs(case["S"]).max())
+
+
+def test_matvec_and_transpose(case):
+    N = case["S"].shape[1]
+    x = synth.rhs_uniform(N, 3)
+    for tr in (False, True):
+        y = acr.acr_matvec(case["h"], _dev(x), transpose=tr).cpu().numpy()
+        ref = (case["A"].T if tr else case["A"]) @ x
+        np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_apply_and_transpose_match_oracle(case):
+    N = case["S"].shape[1]
+    eps = case["eps"]
+    r = synth.rhs_uniform(N, 5)
+    z = acr.acr_apply(case["h"], _dev(r)).cpu().numpy()
+    zo = case["H"].apply(r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    zt = acr.acr_apply_T(case["h"], _dev(r)).cpu().numpy()
+    zto = case["H"].apply_T(r)
+    errt = np.linalg.norm(zt - zto) / np.linalg.norm(zto)
+    print(f"  apply vs oracle {err:.2e}, apply_T vs oracle {errt:.2e}")
+    assert err <= 10 * eps and errt <= 10 * eps, (err, errt)
+    y = synth.rhs_uniform(N, 6)
+    zy = acr.acr_apply(case["h"], _dev(y)).cpu().numpy()
+    assert abs(zt @ y - r @ zy) <= 1e-12 * np.linalg.norm(zt) * np.linalg.norm(y)
+
+
+def test_gmres_solution(case):
+    N = case["S"].shape[1]
+    b = synth.rhs_uniform(N, 10)
+    x_ref = spla.spsolve(case["A"].tocsc(), b)
+    x, info = acr.krylov_solve(case["h"], _dev(b), method=acr.GMRES, restart=50, rtol=1e-12, maxit=300)
+    err = np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)
+    print(f"  GMRES {info['iters']} iterations, error {err:.2e}")
+    assert info["relres_true"] <= 1e-12 and err <= 1e-8
+
+
+def test_stats(case):
+    st = acr.acr_stats(case["h"])
+    assert st["levels"] == len(case["H"].levels) + 1 and st["rank_overflow"] == 0
+    # every level-0 coupling is a stored H-matrix: 2 (nz - 1) of them plus the inverses
+    nz = case["n"][2]
+    assert st["factors"] >= 2 * (nz - 1) + nz // 2
+
+
+def test_near_singular_reduced_system():
+    """19 x 17 x 8 at f = 2.5, eps 1e-4: a reduced plane system is nearly
+    singular, and the oracle's own preconditioner is far from the exact
+    inverse (relative difference about 1.8).  The GPU's must be no worse
+    than ten times the oracle's distance to the exact inverse, and GMRES
+    must still reach the sparse direct solution."""
+    nx, ny, nz, fr, eps = 19, 17, 8, 2.5, 1e-4
+    c = fem27.waveguide_velocity(nx, ny, nz)
+    om = 2.0 * np.pi * fr
+    S = fem27.stencil27(nx, ny, nz, c, om)
+    A = fem27.to_sparse27(S, nx, ny, nz).tocsc()
+    H = hacr.HACR(S, nx, ny, nz, eps=eps, eta=1.0, leaf=32)
+    h = acr.acr_setup(nx, ny, nz, acr.HELMHOLTZ_FEM27, c=_dev(c), omega=om, eps=eps, eta=1.0)
+    r = synth.rhs_uniform(nx * ny * nz, 5)
+    x = spla.spsolve(A, r)
+    e_or = np.linalg.norm(H.apply(r) - x) / np.linalg.norm(x)
+    e_gpu = np.linalg.norm(acr.acr_apply(h, _dev(r)).cpu().numpy() - x) / np.linalg.norm(x)
+    print(f"  distance to the exact inverse: oracle {e_or:.2e}, GPU {e_gpu:.2e}")
+    assert e_or > 100 * eps and e_gpu <= 10 * e_or
+    xs, info = acr.krylov_solve(h, _dev(r), method=acr.GMRES, restart=50, rtol=1e-12, maxit=300)
+    assert np.linalg.norm(xs.cpu().numpy() - x) <= 1e-8 * np.linalg.norm(x), info
