@@ -184,6 +184,11 @@ typedef struct {
     double leaf_inverse_flops;             /* 2 m^3 per m x m dense diagonal leaf inverted
                                               (LU with partial pivoting and inverse), always
                                               counted; setup_flops = the classes + this */
+    double bytes_apply_image;              /* device bytes of the apply images: every H-matrix
+                                              that acr_apply multiplies, stored a second time
+                                              row segment by row segment (its dense leaves and U
+                                              factors) for the row kernel; part of
+                                              bytes_allocated, not of bytes_factors */
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

@@ -175,11 +175,29 @@ void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start
     ln.dbuf_bytes = 0;
   }
   scratch_stride = 0;
+  const bool log = [] {
+    const char* e = getenv("ACR_LOG");
+    return e && e[0] == '1';
+  }();
+  auto t_mark = std::chrono::steady_clock::now();
+  auto mark = [&](const char* what) {
+    if (!log) return;
+    HIPCHK(hipStreamSynchronize(s));
+    const auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "[acr] %s: %.3f s\n", what, std::chrono::duration<double>(now - t_mark).count());
+    fflush(stderr);
+    t_mark = now;
+  };
   build_apply_jobs();
+  mark("apply jobs");
+  build_apply_image(s);
+  mark("apply images");
   tune_apply(s);
   HIPCHK(hipStreamSynchronize(s));
+  mark("apply tuning");
   const int retries = st.retries, overflow = st.rank_overflow, maxr = st.max_rank_all;
   compute_stats();
+  mark("statistics");
   st.retries = retries;
   st.rank_overflow = overflow;
   st.max_rank_all = std::max(st.max_rank_all, maxr);  // the largest rank produced, stored or not
@@ -263,9 +281,7 @@ void Handle::upload_leaf_tables() {
       acc += G.lf[i].cap;
     }
   sstride = std::max<int64_t>(acc, 1);
-  if (d_lr_leaves) dfree(d_lr_leaves);
   if (d_soff) dfree(d_soff);
-  d_lr_leaves = upload(lrl);
   d_soff = upload(soff);
   // coefficient kernel order: low-rank leaves by the lane-group class of
   // the factor length it reduces over (n for V^T x, m for U^T x)
@@ -757,6 +773,88 @@ void Handle::build_apply_jobs() {
   coef = dnew<double>((size_t)std::max(max_jobs, 1) * 2 * sstride);
 }
 
+// Apply images (see SegImg): every H-matrix that an apply phase multiplies
+// gets, per row segment, its rows of the dense leaves and of the U factors
+// as one contiguous run of columns (the row image, for H x), and per column
+// segment the transposed dense leaves and the rows of the V factors (the
+// column image, for H^T x), so the segment kernel streams a segment with
+// 16-byte loads and no per-leaf descriptors.  Sized on the host from each
+// instance's ranks, filled on the device.
+void Handle::build_apply_image(hipStream_t s) {
+  for (void* p : {(void*)img_data, (void*)img_widx, (void*)d_img_seg, (void*)d_img_of_inst}) dfree(p);
+  img_data = nullptr;
+  img_widx = nullptr;
+  d_img_seg = nullptr;
+  d_img_of_inst = nullptr;
+  img_tab_half = 0;
+  img_bytes = 0.0;
+  std::vector<int32_t> img_of(inst.size(), -1), ids;
+  for (const std::vector<PhaseJobs>* phv : {&ph_apply, &ph_applyT})
+    for (const PhaseJobs& pj : *phv)
+      for (const MvJob& J : pj.h)
+        for (const MvTerm& t : J.t)
+          if (t.inst >= 0 && img_of[t.inst] < 0) {
+            img_of[t.inst] = (int32_t)ids.size();
+            ids.push_back(t.inst);
+          }
+  if (ids.empty()) return;
+  const int nseg = (int)G.leaf_clusters.size();
+  const int64_t half = (int64_t)ids.size() * nseg;
+  // dense columns per segment (geometry only): n of each dense leaf in the
+  // row image, m in the column image
+  std::vector<int> nd_row(nseg, 0), nd_col(nseg, 0), seg_ld(nseg);
+  for (int sg = 0; sg < nseg; ++sg) {
+    const Cluster& c = G.cl[G.leaf_clusters[sg]];
+    seg_ld[sg] = ((c.hi - c.lo) + 3) & ~3;
+    for (int l : G.rows_of_seg[sg])
+      if (G.lf[l].fmt != LF_LR) nd_row[sg] += G.lf[l].n;
+    for (int l : G.cols_of_seg[sg])
+      if (G.lf[l].fmt != LF_LR) nd_col[sg] += G.lf[l].m;
+  }
+  std::vector<SegImg> tab(2 * half);
+  std::vector<int32_t> rk(G.lf.size());
+  int64_t doff = 0, woff = 0;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    HIPCHK(hipMemcpy(rk.data(), inst[ids[i]].rank, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int tr = 0; tr < 2; ++tr)
+      for (int sg = 0; sg < nseg; ++sg) {
+        int nu = 0;
+        for (int l : (tr ? G.cols_of_seg[sg] : G.rows_of_seg[sg]))
+          if (G.lf[l].fmt == LF_LR) nu += rk[l];
+        SegImg& e = tab[tr * half + (int64_t)i * nseg + sg];
+        e.data_off = doff;
+        e.widx_off = woff;
+        e.nd = tr ? nd_col[sg] : nd_row[sg];
+        e.nu = nu;
+        doff += (int64_t)(e.nd + nu) * seg_ld[sg];
+        woff += e.nd + nu;
+      }
+  }
+  const size_t esz = fp32 ? 4 : 8;
+  img_data = dmalloc((size_t)doff * esz);
+  img_widx = dnew<int32_t>((size_t)woff);
+  d_img_seg = upload(tab);
+  d_img_of_inst = upload(img_of);
+  img_tab_half = half;
+  int32_t* d_ids = upload(ids);
+  sync_tables();
+  for (int tr = 0; tr < 2; ++tr) {
+    const int32_t* lp = tr ? d_cols_ptr : d_rows_ptr;
+    const int32_t* li = tr ? d_cols_idx : d_rows_idx;
+    if (fp32)
+      launch_img_build<float>((float* const*)d_inst_base, d_inst_rank, d_inst_off, d_leaves, d_soff, d_seg_lo, lp, li,
+                              nseg, tr, d_ids, d_img_seg + tr * half, (int)ids.size(), (float*)img_data, img_widx, s);
+    else
+      launch_img_build<double>((double* const*)d_inst_base, d_inst_rank, d_inst_off, d_leaves, d_soff, d_seg_lo, lp,
+                               li, nseg, tr, d_ids, d_img_seg + tr * half, (int)ids.size(), (double*)img_data,
+                               img_widx, s);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  dfree(d_ids);
+  img_bytes = (double)doff * esz + (double)woff * 4 + (double)tab.size() * sizeof(SegImg);
+}
+
 void Handle::apply(const std::vector<const double*>& r, const std::vector<double*>& out, bool transpose, int prob,
                    hipStream_t s) {
   sync_tables();
@@ -774,8 +872,8 @@ void Handle::apply(const std::vector<const double*>& r, const std::vector<double
   HIPCHK(hipGetLastError());
 }
 
-// One apply phase: the coefficient kernel and the row (column) kernel of
-// its jobs.  ri selects the coefficient kernel's schedule (0: one leaf round
+// One apply phase: the coefficient kernel and the segment kernel of its
+// jobs.  ri selects the coefficient kernel's schedule (0: one leaf round
 // per lane group, 1: four); -1 takes it from the phase size.  The schedule
 // changes which wavefront handles a leaf, not the arithmetic of any leaf,
 // so results do not depend on it.
@@ -784,9 +882,7 @@ void Handle::launch_phase(const PhaseJobs& pj, int ri, hipStream_t s) {
     using T = decltype(tag);
     MvArgs<T> a{};
     a.leaves = d_leaves;
-    a.lr_leaves = d_lr_leaves;
     a.soff = d_soff;
-    a.nlr = G.nlr;
     a.sstride = sstride;
     a.jobs = pj.d;
     a.njobs = pj.n;
@@ -808,11 +904,11 @@ void Handle::launch_phase(const PhaseJobs& pj, int ri, hipStream_t s) {
     a.inst_off = d_inst_off;
     a.coef = coef;
     a.seg_lo = d_seg_lo;
-    a.rows_ptr = d_rows_ptr;
-    a.rows_idx = d_rows_idx;
-    a.cols_ptr = d_cols_ptr;
-    a.cols_idx = d_cols_idx;
     a.nseg = (int)G.leaf_clusters.size();
+    a.img_data = (const T*)img_data;
+    a.img_widx = img_widx;
+    a.img_seg = d_img_seg + (pj.trans ? img_tab_half : 0);
+    a.img_of_inst = d_img_of_inst;
     launch_mv<T>(a, s);
   };
   if (fp32)
@@ -956,6 +1052,7 @@ void Handle::compute_stats() {
   s.bytes_factors = total;
   s.bytes_allocated = (double)bytes_alloc;
   s.bytes_per_apply = apply_bytes;
+  s.bytes_apply_image = img_bytes;
   st = s;
 }
 

@@ -153,6 +153,7 @@ Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_wor
       if (c.lo >= L.c0 && c.hi <= L.c0 + L.n) g.cols_of_seg[k].push_back(l);
     }
   }
+  for (const Leaf& L : g.lf) ++(L.fmt == LF_LR ? g.nlr : g.ndense);
   return g;
 }
 

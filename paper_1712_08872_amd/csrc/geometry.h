@@ -82,8 +82,8 @@ struct Geometry {
   std::string summary() const;
 };
 
-// Build (or fetch from a process-wide cache) the geometry of a plane shape.
-// Capacities are set separately by assign_caps.
+// Build the geometry of a plane shape.  Capacities are set separately by
+// assign_caps.
 // diag9: the plane blocks also couple diagonal in-plane neighbours (the
 // 27-point operator), which level 0 must hold exactly as well.
 Geometry build_geometry(int nx, int ny, int leaf_size, double eta, int dense_work, bool diag9 = false);

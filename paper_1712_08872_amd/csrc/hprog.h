@@ -127,12 +127,25 @@ struct MvJob {
   MvTerm t[2];
 };
 
+// Apply image of one H-matrix for one segment (leaf cluster) of R indices,
+// as columns of ldR = pad4(R) elements (zero padding), contiguous from
+// data_off.  Row image (H x): the segment's rows of every leaf covering
+// them, first the nd columns of the dense leaves (weights from the term's
+// input vector), then the nu columns of the U factors (weights from the
+// term's coefficients V^T x).  Column image (H^T x): the segment's columns
+// of the dense leaves covering them, transposed (weights from the input),
+// then the segment's rows of the V factors (weights from U^T x).
+// widx[widx_off + c] is the weight index of column c.
+struct SegImg {
+  int64_t data_off;
+  int64_t widx_off;
+  int32_t nd, nu;
+};
+
 template <typename T>
 struct MvArgs {
   const DLeaf* leaves;
-  const int32_t* lr_leaves;   // ids of low-rank leaves
   const int64_t* soff;        // per leaf: offset of its coefficient slot (sum of caps)
-  int32_t nlr;
   int64_t sstride;            // per (job, term) coefficient stride
   const MvJob* jobs;
   int32_t njobs;
@@ -151,13 +164,15 @@ struct MvArgs {
   int32_t* const* inst_rank;
   const int64_t* const* inst_off;  // packed per-leaf offsets (every factor is packed)
   double* coef;               // [njobs * 2 * sstride]
-  // segment -> leaves covering it (rows for N, columns for T)
-  const int32_t* seg_lo;      // [nseg + 1] H-order bounds of leaf clusters
-  const int32_t* rows_ptr;
-  const int32_t* rows_idx;
-  const int32_t* cols_ptr;
-  const int32_t* cols_idx;
+  const int32_t* seg_lo;      // [nseg + 1] H-order bounds of the leaf clusters (segments)
   int32_t nseg;
+  // apply images of the phase's direction (row images for H x, column
+  // images for H^T x): instance i's entry for a segment is
+  // img_seg[img_of_inst[i] * nseg + segment]
+  const T* img_data;
+  const int32_t* img_widx;
+  const SegImg* img_seg;
+  const int32_t* img_of_inst;
 };
 
 }  // namespace acr

@@ -1,19 +1,24 @@
 // Batched H-matrix-vector products for the preconditioner sweeps.
 //
 // The apply phase of ACR consists of H-matrix-vector products only
-// (Sec. 5.3.1): each step of the forward/backward
-// substitution multiplies every plane of a cyclic-reduction level by a
-// stored H-matrix (Dinv_i or a coupling).  A *job* computes
+// (Sec. 5.3.1): each step of the forward/backward substitution multiplies
+// every plane of a cyclic-reduction level by a stored H-matrix (Dinv_i or a
+// coupling).  A *job* computes
 //     y = base + sum_t alpha_t op_t(H_t) x_t
 // for one plane, with up to two terms (op = identity or transpose; a term
-// may also be a diagonal vector, the level-0 z-couplings).  Every stored
-// H-matrix is packed (exact ranks, leading dimensions padded to a multiple
-// of 4 elements, leaves 4-element aligned), so columns stream with 16-byte
-// loads.  Three wavefront-level kernels, no block barriers:
-//   mv_coef_kernel : s = V^T x (or U^T x) per (job term, low-rank leaf);
-//                    a power-of-two group of lanes per column;
-//   mv_rows_kernel : y = sum D x + sum U s per (job, row segment);
-//   mv_cols_kernel : y = sum D^T x + sum V s per (job, column segment).
+// may also be a diagonal vector, the level-0 z-couplings).  Two kernels per
+// phase, no atomics:
+//   mv_coef_kernel : s = V^T x (or U^T x) per (job term, low-rank leaf) on
+//                    the packed factors (exact ranks, leading dimensions
+//                    padded to 4, 16-byte column loads), whose V (U)
+//                    columns are contiguous; a power-of-two group of lanes
+//                    per column;
+//   mv_seg_kernel  : y = sum D x + sum U s per (job, row segment), or
+//                    y = sum D^T x + sum V s per (job, column segment), from
+//                    the apply images: per segment and H-matrix, every
+//                    column the segment needs stored contiguously with the
+//                    index of its weight (see SegImg), built once at the end
+//                    of the setup by img_build_kernel.
 // Sums are formed in a fixed order (deterministic results).  Arithmetic is
 // FP64; the factor loads are FP32 in mixed precision.
 #include <hip/hip_runtime.h>
@@ -27,23 +32,6 @@ namespace acr {
 
 __device__ __forceinline__ int pad4(int x) { return (x + 3) & ~3; }
 __device__ __forceinline__ int imin_(int a, int b) { return a < b ? a : b; }
-
-// Four consecutive elements (16-byte aligned for float, 32 for double).
-__device__ __forceinline__ void load4(const float* p, double* o) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
-  o[0] = v.x;
-  o[1] = v.y;
-  o[2] = v.z;
-  o[3] = v.w;
-}
-__device__ __forceinline__ void load4(const double* p, double* o) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
-  o[0] = a.x;
-  o[1] = a.y;
-  o[2] = b.x;
-  o[3] = b.y;
-}
 
 // Four consecutive elements in the factor's own precision (16-byte loads).
 template <typename T>
@@ -64,22 +52,6 @@ __device__ __forceinline__ void load4raw<double>(const double* p, double* o) {
   o[1] = a.y;
   o[2] = b.x;
   o[3] = b.y;
-}
-
-// lanes per column: the power of two covering ceil(len / 4) quads, <= 64
-__device__ __forceinline__ int lanes_per_col(int len) {
-  int g = 1;
-  while (g * 4 < len && g < 64) g <<= 1;
-  return g;
-}
-
-// Uniform copies of lane i's value (the descriptors of a chunk of leaves
-// are fetched lane-parallel, then walked one leaf at a time).
-__device__ __forceinline__ int bcast(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
-__device__ __forceinline__ int64_t bcast64(int64_t v, int i) {
-  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, i);
-  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), i);
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
 // Elements of a factor column per lane in the coefficient kernel: 4 for
@@ -246,277 +218,189 @@ __global__ __launch_bounds__(256) void mv_coef_kernel(MvArgs<T> A) {
   }
 }
 
-// Lane-parallel descriptors of up to 64 leaves of a segment list.
-struct SegDesc {
-  int m, n, r0, c0, fmt, k;
-  int64_t off, so;
-};
-
+// ------------------------------------------------------------ apply images
+// Image of (image i, segment s), one block each.  Row image (trans = 0):
+// rows [lo, lo + R) of the segment's dense leaves, then of the U factors of
+// its low-rank leaves, as columns of ldR = pad4(R) elements (padding rows
+// zero); the weight index of dense column c is c0 + c (the term's input
+// vector), of U column a it is soff + a (the term's coefficients V^T x).
+// Column image (trans = 1), for H^T: the segment's columns [lo, lo + R) of
+// the dense leaves covering them, transposed (row r of the leaf becomes a
+// column, weight index r0 + r), then the rows [lo, lo + R) of the V factors
+// (weight index soff + a: the coefficients U^T x).  Leaves in the order of
+// the segment's leaf list; the host sized every segment from the same ranks.
 template <typename T>
-__device__ __forceinline__ SegDesc seg_desc(const MvArgs<T>& A, const int32_t* idx, int e, int inst) {
-  SegDesc d;
-  const int l = idx[e];
-  const DLeaf L = A.leaves[l];
-  d.m = L.m;
-  d.n = L.n;
-  d.r0 = L.r0;
-  d.c0 = L.c0;
-  d.fmt = L.fmt;
-  d.k = L.fmt ? A.inst_rank[inst][l] : 0;
-  d.off = A.inst_off[inst][l];
-  d.so = L.fmt ? A.soff[l] : 0;
-  return d;
-}
-
-// Columns per unit of the row kernel: two for FP32 factors (32 bytes per
-// lane per unit, as one column of FP64 factors).
-template <typename T>
-struct RowCols {
-  static constexpr int value = sizeof(T) == 8 ? 1 : 2;
-};
-
-// One (leaf, pass) unit of the row kernel for this lane: rows 4q..4q+3 of
-// the segment in columns c + s cpp (s < NC) of a dense leaf or of a U
-// factor (raw factor values), and the weights of those columns (x for a
-// dense leaf, the coefficients s = V^T x for U).
-template <typename T>
-struct RowUnit {
-  static constexpr int NC = RowCols<T>::value;
-  T v[NC][4];
-  double w[NC];
-};
-
-template <typename T>
-__device__ __forceinline__ void row_unit_load(const T* P, int ldm, int ro, int c, int cpp, int ncols,
-                                              const double* wp, int q, int R, bool act, RowUnit<T>& u) {
-#pragma unroll
-  for (int s = 0; s < RowUnit<T>::NC; ++s) {
-    const int cs = c + s * cpp;
-    if (act && cs < ncols) {
-      const T* col = P + (int64_t)cs * ldm + ro + 4 * q;
-      if ((ro & 3) == 0) {
-        load4raw(col, u.v[s]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) u.v[s][r] = (4 * q + r < R) ? col[r] : T{};
+__global__ __launch_bounds__(256) void img_build_kernel(T* const* inst_base, int32_t* const* inst_rank,
+                                                        const int64_t* const* inst_off, const DLeaf* leaves,
+                                                        const int64_t* soff, const int32_t* seg_lo,
+                                                        const int32_t* list_ptr, const int32_t* list_idx, int nseg,
+                                                        int trans, const int32_t* img_inst, const SegImg* img_seg,
+                                                        int nimg, T* img_data, int32_t* img_widx) {
+  __shared__ int s_cnt[2][256];  // running column counts: dense leaves, low-rank leaves
+  __shared__ int s_cur[256];     // first image column of each leaf of the chunk
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int64_t b = blockIdx.x; b < (int64_t)nimg * nseg; b += gridDim.x) {
+    const int im = (int)(b / nseg), sg = (int)(b - (int64_t)im * nseg);
+    const int X = img_inst[im];
+    const SegImg si = img_seg[b];
+    const int lo = seg_lo[sg], R = seg_lo[sg + 1] - lo, ldR = pad4(R);
+    T* out = img_data + si.data_off;
+    int32_t* wi = img_widx + si.widx_off;
+    const T* base = inst_base[X];
+    const int e0 = list_ptr[sg], ne = list_ptr[sg + 1] - e0;
+    int carry0 = 0, carry1 = 0;  // columns of the chunks before (uniform)
+    for (int ec = 0; ec < ne; ec += 256) {
+      // each thread sizes one leaf; prefix sums place dense leaves first,
+      // then the low-rank factors, each group in list order
+      int fmt = 0, nc = 0;
+      if (ec + tid < ne) {
+        const int l = list_idx[e0 + ec + tid];
+        const DLeaf L = leaves[l];
+        fmt = L.fmt;
+        nc = fmt ? inst_rank[X][l] : (trans ? L.m : L.n);
       }
-      u.w[s] = wp[cs];
-    } else {
-      u.v[s][0] = u.v[s][1] = u.v[s][2] = u.v[s][3] = T{};
-      u.w[s] = 0.0;
+      s_cnt[0][tid] = fmt ? 0 : nc;
+      s_cnt[1][tid] = fmt ? nc : 0;
+      __syncthreads();
+      for (int o = 1; o < 256; o <<= 1) {
+        const int a0 = tid >= o ? s_cnt[0][tid - o] : 0, a1 = tid >= o ? s_cnt[1][tid - o] : 0;
+        __syncthreads();
+        s_cnt[0][tid] += a0;
+        s_cnt[1][tid] += a1;
+        __syncthreads();
+      }
+      s_cur[tid] = fmt ? si.nd + carry1 + s_cnt[1][tid] - nc : carry0 + s_cnt[0][tid] - nc;
+      const int tot0 = s_cnt[0][255], tot1 = s_cnt[1][255];
+      __syncthreads();
+      // wavefront w copies leaves w, w + 4, ... of the chunk
+      const int nchunk = ne - ec < 256 ? ne - ec : 256;
+      for (int t = w; t < nchunk; t += 4) {
+        const int l = list_idx[e0 + ec + t];
+        const DLeaf L = leaves[l];
+        const int k = L.fmt ? inst_rank[X][l] : 0;
+        const int ldm = pad4(L.m), ldn = pad4(L.n), cur = s_cur[t];
+        const T* src = base + inst_off[X][l];
+        int ncl;
+        int64_t off0, cstride, rstride;
+        if (!trans) {  // dense columns or U columns, rows lo - r0 ...
+          ncl = L.fmt ? k : L.n;
+          off0 = lo - L.r0;
+          cstride = ldm;
+          rstride = 1;
+        } else if (L.fmt) {  // V columns, rows lo - c0 ...
+          ncl = k;
+          src += (int64_t)ldm * k;
+          off0 = lo - L.c0;
+          cstride = ldn;
+          rstride = 1;
+        } else {  // rows of the dense leaf, columns lo - c0 ...
+          ncl = L.m;
+          off0 = (int64_t)(lo - L.c0) * ldm;
+          cstride = 1;
+          rstride = ldm;
+        }
+        for (int idx = lane; idx < ncl * ldR; idx += 64) {
+          const int c = idx / ldR, r = idx - c * ldR;
+          out[(int64_t)(cur + c) * ldR + r] = r < R ? src[off0 + (int64_t)c * cstride + (int64_t)r * rstride] : T{};
+          if (r == 0) wi[cur + c] = L.fmt ? (int32_t)(soff[l] + c) : (trans ? L.r0 : L.c0) + c;
+        }
+      }
+      carry0 += tot0;
+      carry1 += tot1;
+      __syncthreads();  // the chunk's LDS is read before the next one overwrites it
     }
   }
 }
 
-// Units in flight per wavefront in the row kernel (a ring: the loads of the
-// next RING-1 units are issued before a unit is accumulated).
-#ifndef ACR_RING32
-#define ACR_RING32 2
-#endif
-#ifndef ACR_RING64
-#define ACR_RING64 3
-#endif
 template <typename T>
-struct RowRing {
-  static constexpr int value = sizeof(T) == 8 ? ACR_RING64 : ACR_RING32;
-};
+void launch_img_build(T* const* inst_base, int32_t* const* inst_rank, const int64_t* const* inst_off,
+                      const DLeaf* leaves, const int64_t* soff, const int32_t* seg_lo, const int32_t* list_ptr,
+                      const int32_t* list_idx, int nseg, int trans, const int32_t* img_inst, const SegImg* img_seg,
+                      int nimg, T* img_data, int32_t* img_widx, hipStream_t s) {
+  const int64_t n = (int64_t)nimg * nseg;
+  const int grid = (int)(n < 16384 ? n : 16384);
+  if (grid > 0)
+    hipLaunchKernelGGL(img_build_kernel<T>, dim3(grid), dim3(256), 0, s, inst_base, inst_rank, inst_off, leaves, soff,
+                       seg_lo, list_ptr, list_idx, nseg, trans, img_inst, img_seg, nimg, img_data, img_widx);
+}
+template void launch_img_build<double>(double* const*, int32_t* const*, const int64_t* const*, const DLeaf*,
+                                       const int64_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
+                                       const int32_t*, const SegImg*, int, double*, int32_t*, hipStream_t);
+template void launch_img_build<float>(float* const*, int32_t* const*, const int64_t* const*, const DLeaf*,
+                                      const int64_t*, const int32_t*, const int32_t*, const int32_t*, int, int,
+                                      const int32_t*, const SegImg*, int, float*, int32_t*, hipStream_t);
 
-// y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi], one block per (job, row
-// segment); wavefront w takes every 4th leaf of the segment's list and the
-// four partial sums are added in wave order (deterministic).  A dense leaf
-// contributes its columns weighted by x, a low-rank leaf the columns of U
-// weighted by its coefficients s = V^T x; lanes map to (row quad, column)
-// with 16-byte loads when the segment starts 4-aligned inside the leaf.
-// The (leaf, column pass) units are walked through a ring, so the loads of
-// several units are in flight while one is accumulated.
+// y[lo:hi] (+)= sum_t alpha_t (H_t x_t)[lo:hi] (row images) or
+// sum_t alpha_t (H_t^T x_t)[lo:hi] (column images), one block per (job,
+// segment).  The segment's image columns of a term are contiguous, so they
+// stream with 16-byte loads: thread = (column group cg, row quad q) with
+// g = ldR / 4 threads per column, cpb = 256 / g columns per block step and U
+// columns in flight per thread; each column is weighted by the input-vector
+// or coefficient entry its index names.  The column groups' partial rows
+// are added in a fixed order (deterministic).
 template <typename T>
-__global__ __launch_bounds__(256) void mv_rows_kernel(MvArgs<T> A) {
-  constexpr int D = RowRing<T>::value;
-  // the walker preloads D - 1 units before the loop; with D = 1 nothing
-  // would be issued and every contribution dropped
-  static_assert(D >= 2, "the row kernel's ring needs at least two slots");
-  __shared__ double red[4][256];
-  __shared__ double part[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double* rw = red[w];
+__global__ __launch_bounds__(256) void mv_seg_kernel(MvArgs<T> A) {
+  constexpr int U = 4;  // columns in flight per thread
+  __shared__ double red[1024];
+  const int tid = threadIdx.x;
   const int64_t nitems = (int64_t)A.njobs * A.nseg;
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int j = (int)(item / A.nseg);
     const int sg = (int)(item - (int64_t)j * A.nseg);
     const MvJob& J = A.jobs[j];
     const int lo = A.seg_lo[sg], R = A.seg_lo[sg + 1] - lo;  // R <= 64
-    const int ldR = pad4(R), g = ldR / 4, cpp = 64 / g;       // quad layout: g lanes per column
-    const int q = lane % g, co = lane / g;
-    const bool qact = co < cpp;
-    const int e0 = A.rows_ptr[sg], ne = A.rows_ptr[sg + 1] - e0;
-    double accq[4] = {0.0, 0.0, 0.0, 0.0};  // rows 4q..4q+3, column group co
-    double accr = 0.0;                      // row `lane` (diagonal terms)
-    for (int tt = 0; tt < 2; ++tt) {
-      const MvTerm& tm = J.t[tt];
-      if (tm.inst < 0) {
-        if (tm.dvec && w == 0 && lane < R) accr += tm.alpha * tm.dvec[lo + lane] * tm.x[lo + lane];
-        continue;
-      }
-      const T* base = A.inst_base[tm.inst];
-      const double* coef = A.coef + (int64_t)(2 * j + tt) * A.sstride;
-      const double al = tm.alpha;
-      for (int eb = w; eb < ne; eb += 256) {
-        const int cnt = imin_(64, (ne - eb + 3) / 4);  // this wave's leaves eb, eb+4, ...
-        if (cnt <= 0) continue;
-        SegDesc d{};
-        if (lane < cnt) d = seg_desc(A, A.rows_idx, e0 + eb + 4 * lane, tm.inst);
-        // the walker: the next unit to load is column pass c0 of leaf i
-        int i = 0, c0 = 0;
-        bool more = true;
-        const T* P = nullptr;
-        const double* wp = nullptr;
-        int ldm = 0, ro = 0, ncols = 0;
-        auto leaf = [&](int ii) {
-          const int fmt = bcast(d.fmt, ii);
-          P = base + bcast64(d.off, ii);
-          ldm = pad4(bcast(d.m, ii));
-          ro = lo - bcast(d.r0, ii);
-          ncols = fmt ? bcast(d.k, ii) : bcast(d.n, ii);
-          wp = fmt ? coef + bcast64(d.so, ii) : tm.x + bcast(d.c0, ii);
-        };
-        int issued = 0;  // real units loaded so far (uniform)
-        auto issue = [&](RowUnit<T>& u) {
-          if (!more) {
-#pragma unroll
-            for (int sc = 0; sc < RowUnit<T>::NC; ++sc) {
-              u.v[sc][0] = u.v[sc][1] = u.v[sc][2] = u.v[sc][3] = T{};
-              u.w[sc] = 0.0;
-            }
-            return;
-          }
-          row_unit_load(P, ldm, ro, c0 + co, cpp, ncols, wp, q, R, qact, u);
-          ++issued;
-          c0 += RowUnit<T>::NC * cpp;
-          if (c0 >= ncols) {
-            c0 = 0;
-            if (++i < cnt)
-              leaf(i);
-            else
-              more = false;
-          }
-        };
-        leaf(0);
-        RowUnit<T> u[D];
-#pragma unroll
-        for (int s = 0; s < D - 1; ++s) issue(u[s]);
-        for (int done = 0; done < issued; ++done) {
-          issue(u[D - 1]);
-#pragma unroll
-          for (int sc = 0; sc < RowUnit<T>::NC; ++sc) {
-            const double wc = al * u[0].w[sc];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) accq[r] += (double)u[0].v[sc][r] * wc;
-          }
-#pragma unroll
-          for (int s = 0; s < D - 1; ++s) u[s] = u[s + 1];
-        }
-      }
-    }
-    // this wave's rows: its column groups in a fixed order
-    if (qact)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) rw[co * ldR + 4 * q + r] = accq[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < R) {
-      double sum = accr;
-      for (int c = 0; c < cpp; ++c) sum += rw[c * ldR + lane];
-      part[w][lane] = sum;
-    }
-    __syncthreads();
-    if (w == 0 && lane < R) {
-      double sum = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-      if (J.base) sum += J.base[lo + lane];
-      J.y[lo + lane] = sum;
-    }
-    __syncthreads();
-  }
-}
-
-// y[lo:hi] (+)= sum_t alpha_t (H_t^T x_t)[lo:hi], one block per (job,
-// column segment), leaves split over the four wavefronts as above.  Dense
-// leaves: one aligned column dot product per lane group (16-byte loads);
-// low-rank leaves: lane = row of V (= output column).
-template <typename T>
-__global__ __launch_bounds__(256) void mv_cols_kernel(MvArgs<T> A) {
-  __shared__ double yacc[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double* yw = yacc[w];
-  const int64_t nitems = (int64_t)A.njobs * A.nseg;
-  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int j = (int)(item / A.nseg);
-    const int sg = (int)(item - (int64_t)j * A.nseg);
-    const MvJob& J = A.jobs[j];
-    const int lo = A.seg_lo[sg], R = A.seg_lo[sg + 1] - lo;
-    const int e0 = A.cols_ptr[sg], ne = A.cols_ptr[sg + 1] - e0;
-    yw[lane] = 0.0;
+    const int ldR = pad4(R), g = ldR >> 2, cpb = 256 / g;
+    const int q = tid % g, cg = tid / g;
+    const bool act = cg < cpb;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     double accr = 0.0;
     for (int tt = 0; tt < 2; ++tt) {
       const MvTerm& tm = J.t[tt];
       if (tm.inst < 0) {
-        if (tm.dvec && w == 0 && lane < R) accr += tm.alpha * tm.dvec[lo + lane] * tm.x[lo + lane];
+        if (tm.dvec && tid < R) accr += tm.alpha * tm.dvec[lo + tid] * tm.x[lo + tid];
         continue;
       }
-      const T* base = A.inst_base[tm.inst];
-      const double* coef = A.coef + (int64_t)(2 * j + tt) * A.sstride;
+      const SegImg si = A.img_seg[(int64_t)A.img_of_inst[tm.inst] * A.nseg + sg];
+      const T* d = A.img_data + si.data_off + 4 * q;
+      const int32_t* wi = A.img_widx + si.widx_off;
+      const double* xw = tm.x;
+      const double* cw = A.coef + (int64_t)(2 * j + tt) * A.sstride;
       const double al = tm.alpha;
-      for (int eb = w; eb < ne; eb += 256) {
-        const int cnt = imin_(64, (ne - eb + 3) / 4);
-        SegDesc d{};
-        if (lane < cnt) d = seg_desc(A, A.cols_idx, e0 + eb + 4 * lane, tm.inst);
-        for (int i = 0; i < cnt; ++i) {
-          const int m = bcast(d.m, i), n = bcast(d.n, i), fmt = bcast(d.fmt, i);
-          const T* P = base + bcast64(d.off, i);
-          const int co0 = lo - bcast(d.c0, i), ldm = pad4(m);
-          if (fmt == 0) {
-            const double* x = tm.x + bcast(d.r0, i);
-            const int g = lanes_per_col(m), cpp = 64 / g;
-            const int q = lane & (g - 1), cg = lane / g;
-            for (int c0 = 0; c0 < R; c0 += cpp) {
-              const int c = c0 + cg;
-              double s = 0.0;
-              if (c < R) {
-                const T* col = P + (int64_t)(co0 + c) * ldm;
-#pragma unroll 4
-                for (int r = 4 * q; r < m; r += 4 * g) {
-                  double v[4];
-                  load4(col + r, v);
+      const int nc = act ? si.nd + si.nu : 0, nd = si.nd;
+      int c = cg;
+      for (; c + (U - 1) * cpb < nc; c += U * cpb) {
+        T v[U][4];
+        int k[U];
 #pragma unroll
-                  for (int e = 0; e < 4; ++e)
-                    if (r + e < m) s += v[e] * x[r + e];
-                }
-              }
-              for (int o = g >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o);
-              if (q == 0 && c < R) yw[c] += al * s;
-            }
-          } else {
-            const int k = bcast(d.k, i);
-            const double* s = coef + bcast64(d.so, i);
-            const T* V = P + (int64_t)ldm * k;
-            const int ldn = pad4(n);
-            if (lane < R) {
-#pragma unroll 8
-              for (int a = 0; a < k; ++a) accr += (double)V[co0 + lane + (int64_t)a * ldn] * (al * s[a]);
-            }
-          }
+        for (int u = 0; u < U; ++u) {
+          load4raw(d + (int64_t)(c + u * cpb) * ldR, v[u]);
+          k[u] = wi[c + u * cpb];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double wt = al * (c + u * cpb < nd ? xw[k[u]] : cw[k[u]]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] += (double)v[u][r] * wt;
         }
       }
+      for (; c < nc; c += cpb) {
+        T v[4];
+        load4raw(d + (int64_t)c * ldR, v);
+        const int k = wi[c];
+        const double wt = al * (c < nd ? xw[k] : cw[k]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] += (double)v[r] * wt;
+      }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    yw[lane] += accr;
+    if (act)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[cg * ldR + 4 * q + r] = acc[r];
     __syncthreads();
-    if (w == 0 && lane < R) {
-      double sum = yacc[0][lane] + yacc[1][lane] + yacc[2][lane] + yacc[3][lane];
-      if (J.base) sum += J.base[lo + lane];
-      J.y[lo + lane] = sum;
+    if (tid < R) {
+      double sum = accr;
+      for (int k = 0; k < cpb; ++k) sum += red[k * ldR + tid];
+      if (J.base) sum += J.base[lo + tid];
+      J.y[lo + tid] = sum;
     }
     __syncthreads();
   }
@@ -565,6 +449,8 @@ template void launch_pack<double>(const double*, const int32_t*, const DLeaf*, i
 template void launch_pack<float>(const float*, const int32_t*, const DLeaf*, int, float*, const int64_t*,
                                  hipStream_t);
 
+// One apply phase: the coefficient kernel (when the phase has low-rank
+// terms), then the segment kernel.
 template <typename T>
 void launch_mv(const MvArgs<T>& a, hipStream_t s) {
   const int64_t n1 = ((int64_t)a.nterms * a.cw[5] + 3) / 4;
@@ -572,12 +458,7 @@ void launch_mv(const MvArgs<T>& a, hipStream_t s) {
   if (g1 > 0) hipLaunchKernelGGL(mv_coef_kernel<T>, dim3(g1), dim3(256), 0, s, a);
   const int64_t n2 = (int64_t)a.njobs * a.nseg;
   const int g2 = (int)(n2 < 16384 ? n2 : 16384);
-  if (g2 > 0) {
-    if (a.trans)
-      hipLaunchKernelGGL(mv_cols_kernel<T>, dim3(g2), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL(mv_rows_kernel<T>, dim3(g2), dim3(256), 0, s, a);
-  }
+  if (g2 > 0) hipLaunchKernelGGL(mv_seg_kernel<T>, dim3(g2), dim3(256), 0, s, a);
 }
 
 template void launch_mv<double>(const MvArgs<double>&, hipStream_t);

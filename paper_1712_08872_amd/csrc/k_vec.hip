@@ -287,10 +287,12 @@ __global__ __launch_bounds__(256) void dot_final_kernel(const double* part, int 
   }
 }
 
-// y = a*x + b*y (a, b read from device scalars when the pointers are set)
+// y = a*x + b*y; with b = 0, y is not read (y = a*x), so a work vector
+// whose memory still holds a non-finite value from earlier use is simply
+// overwritten (0 * Inf would be NaN)
 __global__ void axpby_kernel(int64_t n, double a, const double* x, double b, double* y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i] + b * y[i];
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
 // w = x - sum_j h[j] V[j]  (GMRES orthogonalisation update; V rows of length n)
@@ -328,7 +330,7 @@ __global__ void lincomb_kernel(int64_t n, int nv, const double* V, int64_t ldv, 
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int j = 0; j < nv; ++j) s += c[j] * V[(int64_t)j * ldv + i];
-    y[i] = s + beta * y[i];
+    y[i] = beta == 0.0 ? s : s + beta * y[i];
   }
 }
 

@@ -48,6 +48,11 @@ void launch_zcoupling(const double* S, int64_t N, int B, int nz, const int32_t* 
                       hipStream_t);
 template <typename T> void launch_mv(const MvArgs<T>&, hipStream_t);
 template <typename T>
+void launch_img_build(T* const* inst_base, int32_t* const* inst_rank, const int64_t* const* inst_off,
+                      const DLeaf* leaves, const int64_t* soff, const int32_t* seg_lo, const int32_t* list_ptr,
+                      const int32_t* list_idx, int nseg, int trans, const int32_t* img_inst, const SegImg* img_seg,
+                      int nimg, T* img_data, int32_t* img_widx, hipStream_t s);
+template <typename T>
 void launch_pack(const T* src, const int32_t* rank, const DLeaf* leaves, int nleaf, T* dst, const int64_t* off,
                  hipStream_t);
 void launch_assemble(int kind, int nx, int ny, int nz, const double* kappa, double ba, double bph, const double* c,
@@ -168,7 +173,7 @@ struct Handle {
   int32_t* d_perm = nullptr;
   int64_t* d_l0map = nullptr;
   int32_t *d_seg_lo = nullptr, *d_rows_ptr = nullptr, *d_rows_idx = nullptr, *d_cols_ptr = nullptr,
-          *d_cols_idx = nullptr, *d_lr_leaves = nullptr;
+          *d_cols_idx = nullptr;
   int64_t* d_soff = nullptr;
   int32_t *d_lr_n = nullptr, *d_lr_t = nullptr;  // low-rank leaves by lane class of n (of m)
   int32_t cls_n[6] = {0}, cls_t[6] = {0};
@@ -237,6 +242,17 @@ struct Handle {
   double *g = nullptr, *w = nullptr, *z = nullptr, *coef = nullptr;
   int max_jobs = 0;
   std::vector<PhaseJobs> ph_apply, ph_applyT;  // all problems at once
+  // apply images of the H-matrices the apply phases use (the segment
+  // kernel's input): data and weight-index arenas, per-(image, segment)
+  // tables (the row images of all images, then their column images for the
+  // transposed phases), image of each instance id (-1: none)
+  void* img_data = nullptr;
+  int32_t* img_widx = nullptr;
+  SegImg* d_img_seg = nullptr;
+  int32_t* d_img_of_inst = nullptr;
+  int64_t img_tab_half = 0;  // entries of the row-image tables
+  double img_bytes = 0.0;
+  void build_apply_image(hipStream_t s);
   // krylov workspace (allocated at the first solve; hres is pinned host memory)
   KrylovBuffers kbuf;
   // statistics

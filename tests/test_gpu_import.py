@@ -55,7 +55,7 @@ def case(request):
         ak.update(beta_amp=60.0, beta_phase=0.9)
     h = acr.acr_import_factors(nx, ny, nz, facs, eps=eps, eta=2.0, leaf_size=leaf, **ak)
     h32 = acr.acr_import_factors(nx, ny, nz, facs, eps=eps, eta=2.0, leaf_size=leaf, precision=acr.MIXED_FP32, **ak)
-    return dict(name=request.param, kind=kind, n=(nx, ny, nz), H=H, h=h, h32=h32, S=S,
+    return dict(name=request.param, kind=kind, n=(nx, ny, nz), leaf=leaf, H=H, h=h, h32=h32, S=S,
                 A=assembly.to_sparse(S, nx, ny, nz))
 
 
@@ -103,6 +103,10 @@ def test_bytes_ranks_and_sizes_equal_the_oracle(case):
     H = case["H"]
     st = acr.acr_stats(case["h"])
     st32 = acr.acr_stats(case["h32"])
+    # the leaf counts of an imported handle are the plane geometry's
+    nx, ny, _ = case["n"]
+    info, _, _ = acr.acr_plane_geometry(nx, ny, eta=2.0, leaf_size=case["leaf"])
+    assert (st["lr_leaves"], st["dense_leaves"]) == (info["lr_leaves"], info["dense_leaves"])
     assert st["bytes_per_apply"] == H.apply_bytes(8)
     assert st32["bytes_per_apply"] == H.apply_bytes(4)
     fl = H.factor_list()
