@@ -110,6 +110,71 @@ def kernel_roofline(name, launches, seconds, flops, peak):
             "total_seconds": round(seconds, 3)}
 
 
+def apply_probe(count, n=127, eps=1e-4):
+    """Setup of the benchmark workload (mixed precision), then `count`
+    applications of the preconditioner (counter passes over the apply
+    kernels: rocprofv3 --pmc ... -- python bench.py --apply-probe K)."""
+    import torch
+    import paper_1712_08872_amd as acr
+    kap_np, f_np = _inputs(n)
+    kap = torch.from_numpy(kap_np.reshape(-1)).cuda()
+    f = torch.from_numpy(f_np).cuda()
+    h = acr.acr_setup(n, n, n, acr.POISSON_HARMONIC, kappa=kap, eps=eps, precision=acr.MIXED_FP32)
+    z = torch.empty_like(f)
+    for _ in range(count):
+        acr.acr_apply(h, f, z)
+    torch.cuda.synchronize()
+    print(json.dumps({"applies": count, "bytes_per_apply": acr.acr_stats(h)["bytes_per_apply"]}), flush=True)
+
+
+def trace_summary(db, command, top=14):
+    """Markdown table of a rocprofv3 --kernel-trace --stats database."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    out = ["# rocprofv3 --kernel-trace --stats summary", "", "Command:", "", "```", command, "```", "",
+           "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows[:top]:
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {calls} | {tot / 1e3:.1f} | {avg:.1f} | {pct:.3f} |")  # the view is in us
+    return "\n".join(out) + "\n"
+
+
+def _counter_per_dispatch(path, regex):
+    import csv
+    import re
+    vals = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if re.search(regex, row["Kernel_Name"]):
+                vals[row["Dispatch_Id"]] = vals.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    return vals
+
+
+def traffic_record(record, fetch, write, cfetch, cwrite, copy_bytes, named, commands):
+    """HBM bytes per launch of each named kernel (name=regex, or
+    name=regex/K for the bytes of all matching dispatches divided by K, e.g.
+    per application) from a FETCH_SIZE and a WRITE_SIZE pass (KiB per
+    dispatch), each scaled by what the same counter reads for a plain copy
+    of copy_bytes bytes (the largest dispatch of the copy-probe passes)."""
+    cf = max(_counter_per_dispatch(cfetch, ".").values())
+    cw = max(_counter_per_dispatch(cwrite, ".").values())
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    out = {"source_sha256": kernel_source_hash(TRAFFIC_RECORDS[record][1]), "copy_bytes": copy_bytes,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": ff, "write_scale": fw, "kernels": {},
+           "commands": commands}
+    for name, spec in named:
+        regex, _, per = spec.partition("/")
+        f = _counter_per_dispatch(fetch, regex)
+        w = _counter_per_dispatch(write, regex)
+        units = float(per) if per else float(len(f))
+        fk, wk = sum(f.values()) / units, sum(w.values()) / units
+        out["kernels"][name] = {"regex": regex, "dispatches": len(f), "units": units,
+                                "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+                                "traffic_bytes_per_launch": fk * 1024.0 * ff + wk * 1024.0 * fw}
+    return out
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for calibrating FETCH_SIZE /
     WRITE_SIZE (rocprofv3 --pmc ... -- python bench.py --copy-probe MIB)."""
@@ -228,13 +293,33 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--apply-probe", type=int, default=0, metavar="K",
+                    help="only set up the workload (mixed) and apply the preconditioner K times (counter passes)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("DB", "COMMAND"),
+                    help="print the markdown summary of a rocprofv3 --kernel-trace --stats database")
+    ap.add_argument("--traffic-record", nargs="+",
+                    metavar="RECORD FETCH WRITE COPY_FETCH COPY_WRITE COPY_BYTES name=regex[/K]",
+                    help="print the calibrated traffic record of counter passes (RECORD: accum or apply); "
+                         "the generating commands are read from stdin, one a line")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(*args.trace_summary), end="")
+        return
+    if args.traffic_record:
+        a = args.traffic_record
+        named = [tuple(x.split("=", 1)) for x in a[6:]]
+        cmds = [ln.rstrip("\n") for ln in sys.stdin if ln.strip()]
+        print(json.dumps(traffic_record(a[0], a[1], a[2], a[3], a[4], float(a[5]), named, cmds), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: this build has no multi-GPU path "
               f"(the plane sharding over several GPUs is a design only)", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.apply_probe:
+        apply_probe(args.apply_probe, args.n, args.eps)
         return
     budget = args.budget
     # ---- CPU leg first: its duration depends on the host, the GPU steps fill what remains

@@ -449,13 +449,36 @@ template void launch_pack<double>(const double*, const int32_t*, const DLeaf*, i
 template void launch_pack<float>(const float*, const int32_t*, const DLeaf*, int, float*, const int64_t*,
                                  hipStream_t);
 
-// One apply phase: the coefficient kernel (when the phase has low-rank
-// terms), then the segment kernel.
+// A phase without H-matrix terms (the level-0 updates with diagonal
+// couplings): y = base + sum_t alpha_t d_t .* x_t elementwise over the
+// jobs' planes, in the order the segment kernel adds them.
+template <typename T>
+__global__ __launch_bounds__(256) void mv_diag_kernel(MvArgs<T> A) {
+  const int64_t B = A.seg_lo[A.nseg];
+  const int64_t n = (int64_t)A.njobs * B;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(g / B);
+    const int64_t i = g - (int64_t)j * B;
+    const MvJob& J = A.jobs[j];
+    double sum = 0.0;
+    for (int tt = 0; tt < 2; ++tt)
+      if (J.t[tt].dvec) sum += J.t[tt].alpha * J.t[tt].dvec[i] * J.t[tt].x[i];
+    if (J.base) sum += J.base[i];
+    J.y[i] = sum;
+  }
+}
+
+// One apply phase: the coefficient kernel and the segment kernel, or the
+// elementwise kernel when the phase has no H-matrix terms.
 template <typename T>
 void launch_mv(const MvArgs<T>& a, hipStream_t s) {
   const int64_t n1 = ((int64_t)a.nterms * a.cw[5] + 3) / 4;
   const int g1 = (int)(n1 < 16384 ? n1 : 16384);
   if (g1 > 0) hipLaunchKernelGGL(mv_coef_kernel<T>, dim3(g1), dim3(256), 0, s, a);
+  if (a.nterms == 0) {  // diagonal terms only
+    if (a.njobs > 0) hipLaunchKernelGGL(mv_diag_kernel<T>, dim3(4096), dim3(256), 0, s, a);
+    return;
+  }
   const int64_t n2 = (int64_t)a.njobs * a.nseg;
   const int g2 = (int)(n2 < 16384 ? n2 : 16384);
   if (g2 > 0) hipLaunchKernelGGL(mv_seg_kernel<T>, dim3(g2), dim3(256), 0, s, a);

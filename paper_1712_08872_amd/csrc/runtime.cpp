@@ -112,7 +112,11 @@ int Handle::new_instance(hipStream_t s) {
   I.packed = false;
   I.packed_bytes = 0;
   table_dirty = true;
-  HIPCHK(hipMemsetAsync(I.buf, 0, bytes, s));
+  // zero the dense leaves (level 0 scatters a sparse pattern into them) and
+  // the ranks; low-rank columns are only ever read below their rank, so the
+  // capacity beyond it (most of the buffer) is left as it is
+  HIPCHK(hipMemsetAsync(I.buf, 0, (size_t)G.dense_elems * esz, s));
+  HIPCHK(hipMemsetAsync(I.rank, 0, G.lf.size() * sizeof(int32_t), s));
   return id;
 }
 

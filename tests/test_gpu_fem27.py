@@ -117,3 +117,33 @@ def test_near_singular_reduced_system():
     assert e_or > 100 * eps and e_gpu <= 10 * e_or
     xs, info = acr.krylov_solve(h, _dev(r), method=acr.GMRES, restart=50, rtol=1e-12, maxit=300)
     assert np.linalg.norm(xs.cpu().numpy() - x) <= 1e-8 * np.linalg.norm(x), info
+
+
+FULL = __import__("os").environ.get("ACR_FULL_SIZE") == "1"
+
+
+@pytest.mark.skipif(not FULL, reason="full-size sweep (minutes of GPU time): ACR_FULL_SIZE=1")
+@pytest.mark.parametrize("fr,eps", [(0.0, 1e-1), (2.0, 1e-3), (4.0, 1e-4)], ids=["f0", "f2", "f4"])
+def test_frequency_sweep_127(fr, eps):
+    """Low to high frequency (Sec. 8.2): the waveguide at 127^3 with the
+    preconditioner accuracy the paper's table pairs with each frequency
+    (f = 0: the Laplacian; f = 4: 24 points per minimum wavelength), mixed
+    precision, eta 1; GMRES(30) to 1e-8 with the residual recomputed by the
+    oracle's 27-point operator.  Iterations, ranks, memory and setup time are
+    printed for the record."""
+    n = 127
+    c = fem27.waveguide_velocity(n)
+    om = 2.0 * np.pi * fr
+    f = synth.rhs_uniform(n ** 3, 61)
+    h = acr.acr_setup(n, n, n, acr.HELMHOLTZ_FEM27, c=_dev(c), omega=om, eps=eps, eta=1.0,
+                      precision=acr.MIXED_FP32)
+    st = acr.acr_stats(h)
+    x, info = acr.krylov_solve(h, _dev(f), method=acr.GMRES, restart=30, rtol=1e-8, maxit=500)
+    print(f"  f={fr} eps={eps}: setup {st['setup_seconds']:.1f} s, max rank {st['max_rank_all']}, factors "
+          f"{st['bytes_factors'] / 1e9:.2f} GB, peak {st['bytes_peak'] / 1e9:.1f} GB, GMRES {info['iters']} iterations")
+    assert info["status"] == 0, info
+    A = fem27.to_sparse27(fem27.stencil27(n, n, n, c, om), n, n, n)
+    r = f - A @ x.cpu().numpy()
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(f)
+    h.close()
+    torch.cuda.empty_cache()
