@@ -210,10 +210,11 @@ def gpu_step(acr, torch, n, kap, f, precision, eps, rtol, eta=2.0, leaf=32):
                   "relres": info["relres_true"], "stats": st}
 
 
-def apply_roofline(acr, torch, h, f, reps=10):
+def apply_roofline(acr, torch, h, f, reps=10, counters=True):
     """Algorithmic bytes per apply over the apply time (HIP events on the
     stream the apply kernels are launched on: torch's current stream, which
-    the binding hands to the library)."""
+    the binding hands to the library).  The counter record is of the mixed
+    apply (counters=False for the FP64 handle: traffic null)."""
     stream = torch.cuda.current_stream()
     z = torch.empty_like(f)
     acr.acr_apply(h, f, z, stream=stream)
@@ -226,7 +227,7 @@ def apply_roofline(acr, torch, h, f, reps=10):
     t = e0.elapsed_time(e1) / 1e3 / reps
     b = acr.acr_stats(h)["bytes_per_apply"]
     gbs = b / t / 1e9
-    traffic = measured_traffic("apply", "acr_apply")
+    traffic = measured_traffic("apply", "acr_apply") if counters else None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic is not None else None,
             "ms_per_apply": round(t * 1e3, 3), "bytes_per_apply": b}
@@ -375,7 +376,7 @@ def main():
         log(f"fp64 step {k}: {r['seconds']:.2f} s (setup {r['setup_s']:.2f}, solve {r['solve_s']:.3f}, "
             f"{r['iters']} iters)")
         if aroof64 is None:
-            aroof64 = apply_roofline(acr, torch, h, f)
+            aroof64 = apply_roofline(acr, torch, h, f, counters=False)
         del h
     torch.cuda.empty_cache()
     c1_gpu = gpu_c1(acr, torch) if cpu is not None else None

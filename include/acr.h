@@ -223,11 +223,18 @@ int32_t acr_num_problems(const acr_handle* h);
  * must not alias r. */
 acr_status acr_apply(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
 
-/* z = M^{-T} r, the exact transpose of the linear map of acr_apply. */
+/* z = M^{-T} r, the exact transpose of the linear map of acr_apply: the
+ * substitution sweeps of Sec. 4.1 in reverse order with every stored
+ * H-matrix transposed (the adjoint solves of the gradient and of A^T x = b).
+ * Arguments, layout and errors as acr_apply. */
 acr_status acr_apply_T(acr_handle* h, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* y = A x (transpose = 0) or A^T x (transpose = 1) with the assembled
- * operator (7- or 27-point); x, y device, N doubles. */
+ * operator (the 7-point discretisations of Sec. 6 eq. poissonEquation, Sec.
+ * 7 eq. codi and Sec. 8, or the 27-point FEM of Sec. 8 eq. HelmVarVel), the
+ * operator the Krylov methods of Sec. 5.3 iterate on; x, y device, N
+ * doubles (a batched handle: all problems concatenated), natural ordering,
+ * y must not alias x.  ACR_E_INVALID for null pointers. */
 acr_status acr_matvec(acr_handle* h, int32_t transpose, const double* x, double* y, void* stream);
 
 /* Copy the assembled stencil to the device buffer out: 7*N doubles in the
@@ -266,8 +273,13 @@ acr_status krylov_solve(acr_handle* h, int32_t method, int32_t restart, int32_t 
 acr_status krylov_solve_static(acr_handle* h, int32_t method, int32_t restart, int32_t transpose, double rtol,
                                int32_t maxit, const double* b, double* x, acr_solve_info* info, void* stream);
 
-/* Adjoint gradient for ACR_POISSON_HARMONIC: dkappa = -lam^T (dA/dkappa) u
- * on the node grid ((nz+2)(ny+2)(nx+2) doubles, overwritten). */
+/* Adjoint gradient for ACR_POISSON_HARMONIC (the operator of Sec. 6 eq.
+ * poissonEquation with the harmonic face average): dkappa = -lam^T
+ * (dA/dkappa) u, the derivative of A u with respect to every node value of
+ * kappa contracted with the adjoint state lam (computed by the caller with
+ * acr_apply_T / krylov_solve(transpose = 1)).  u, lam: device, N doubles;
+ * dkappa: device, the node grid ((nz+2)(ny+2)(nx+2) doubles, overwritten).
+ * ACR_E_INVALID for other problem kinds or null pointers. */
 acr_status acr_grad_kappa(acr_handle* h, const double* u, const double* lam, double* dkappa,
                           void* stream);
 
@@ -356,7 +368,11 @@ typedef struct {
 acr_status acr_import_factors(const acr_problem* p, const acr_options* o, const acr_factor_blob* blob, void* stream,
                               acr_handle** out);
 
-/* Statistics of a handle (ranks, bytes, flops, timings). */
+/* Statistics of a handle: ranks and bytes per level (the memory footprint
+ * of Sec. 6.4 and Sec. 8.3: the sum of the stored H-matrices at their
+ * actual ranks), algorithmic bytes per application, setup flops by class
+ * (the operation count of Sec. 6.4), timings.  st: host, filled on
+ * success; ACR_E_INVALID for null pointers. */
 acr_status acr_stats(const acr_handle* h, acr_stats_t* st);
 
 /* Release a handle and all device memory it owns (NULL is ignored). */
