@@ -1164,9 +1164,10 @@ __device__ void dense_add_outer(T* C, const DLeaf& tc, const T* Us, const T* Vs,
 }
 
 // Dense accumulation C += sum of the target's pieces (C column-major,
-// leading dimension tc.m).  Low-rank pieces are expanded `take` columns at a
-// time into the staging columns [0, take) of Us / Vs and added as outer
-// products.
+// leading dimension tc.m).  The columns of consecutive low-rank pieces are
+// staged side by side in Us / Vs and added as one outer product whenever
+// the KC staging columns are full (and at the end): one read-modify-write
+// of C per KC columns rather than per piece.
 template <bool BF, typename T, typename LT>
 __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, const DLeaf& tc, T* C, T* Us, T* Vs,
                              LT& L) {
@@ -1176,10 +1177,22 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
   CT* S2c = reinterpret_cast<CT*>(L.S2);
   const int tid = threadIdx.x;
   unsigned long long* prof = A.prof;
-  for (int p = tg.p0; p < tg.p1; ++p) {
+  // Columns of low-rank pieces are staged at [K, K + take) of Us / Vs; the
+  // outer product has one call site (inlined twice, the kernel spills).
+  int K = 0, j0 = 0;
+  for (int p = tg.p0; p < tg.p1 || K > 0;) {
+    if (p == tg.p1 || K == KC) {
+      const long long to = clock64();
+      dense_add_outer<BF>(C, tc, Us, Vs, K, L);
+      PROF_ADD(PS_OUTER, clock64() - to);
+      FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * K);
+      K = 0;
+      continue;
+    }
     const Piece P = A.pieces[p];
     const long long tpd = clock64();
     if (P.kind == PK_DD) {
+      ++p;
       const int xi = inst_of(A, b, P.xrole), yi = inst_of(A, b, P.yrole);
       if (xi < 0 || yi < 0) continue;
       const DLeaf x = A.leaves[P.xleaf], y = A.leaves[P.yleaf];
@@ -1203,6 +1216,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       }
       PROF_ADD(PS_DDP, clock64() - tpd);
     } else if (P.kind == PK_COPY && A.leaves[P.xleaf].fmt == 0) {
+      ++p;
       const int si = inst_of(A, b, P.xrole);
       if (si < 0) continue;
       const LeafRef<T> sr = leaf_ref(A, si, P.xleaf, A.leaves[P.xleaf]);
@@ -1218,14 +1232,15 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       }
       __syncthreads();
     } else {
+      // a low-rank piece, `take` of its columns per pass
       const int w = piece_width(A, b, P);
-      for (int j0 = 0; j0 < w; j0 += KC) {
-        int take = imin(KC, w - j0);
-        piece_columns<BF>(A, b, P, tc, j0, take, Us, Vs, 0, L);
-        const long long to = clock64();
-        dense_add_outer<BF>(C, tc, Us, Vs, take, L);
-        PROF_ADD(PS_OUTER, clock64() - to);
-        FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * take);
+      const int take = imin(KC - K, w - j0);
+      if (take > 0) piece_columns<BF>(A, b, P, tc, j0, take, Us, Vs, K, L);
+      K += imax(take, 0);
+      j0 += imax(take, 0);
+      if (j0 >= w) {
+        j0 = 0;
+        ++p;
       }
     }
   }
@@ -1391,11 +1406,12 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
 }
 
 // The accumulate-only kernel needs only the staging tiles (FP32 tiles for
-// FP32 factors): with narrow rounds, trade a little spilling for six
-// resident wavefronts per SIMD (measured best among 4, 5, 6).
+// FP32 factors): with narrow rounds, four resident wavefronts per SIMD
+// (128 VGPRs, no spilling with FP32 factors; measured best among 4, 5, 6
+// once the staged piece columns are batched: 6 spills 300 B per lane).
 #if KCV <= 40
 #ifndef DENSE_WPE
-#define DENSE_WPE 6
+#define DENSE_WPE 4
 #endif
 #define DENSE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(DENSE_WPE, DENSE_WPE)))
 #else
