@@ -31,7 +31,11 @@ Also printed (same JSON line):
                     bound): algorithmic flops per launch / mean launch
                     duration (HIP events on its stream), against 78.6
                     TFLOP/s (truncating kernel, FP64 cores) or 157.3 TFLOP/s
-                    (accumulate-only kernel, FP32 products);
+                    (accumulate-only kernel, FP32 products), with the
+                    kernel's algorithmic bytes per launch (operand and target
+                    entries, counted in the kernel) beside its counter-measured
+                    HBM traffic, and its matrix-core use (MFMA flops, busy
+                    percentage) from a committed counter pass;
                     roofline_second_kernel -- the other one
   apply_roofline -- the preconditioner application (HBM bound):
                     algorithmic bytes per apply / apply time vs 8 TB/s, for
@@ -72,6 +76,8 @@ TRAFFIC_RECORDS = {
     "accum": (os.path.join(ROOT, "profiles", "accum_kernel_traffic.json"), ("k_harith.hip", "hprog.h")),
     "apply": (os.path.join(ROOT, "profiles", "apply_kernels_traffic.json"), ("k_apply.hip", "hprog.h")),
 }
+# matrix-core use of the H-arithmetic kernels from a rocprofv3 --pmc pass
+MFMA_RECORD = (os.path.join(ROOT, "profiles", "accum_kernel_mfma.json"), ("k_harith.hip", "hprog.h"))
 
 
 def kernel_source_hash(files):
@@ -96,18 +102,41 @@ def measured_traffic(record, kernel):
     return rec.get("kernels", {}).get(kernel, {}).get("traffic_bytes_per_launch")
 
 
-def kernel_roofline(name, launches, seconds, flops, peak):
+def measured_mfma(kernel):
+    """Matrix-core record of `kernel` (committed counter pass), or None when
+    absent or taken on a different kernel source."""
+    path, files = MFMA_RECORD
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash(files):
+        return None
+    return rec.get("kernels", {}).get(kernel)
+
+
+def kernel_roofline(name, launches, seconds, flops, peak, abytes=None):
     """Algorithmic flops per launch over the mean launch duration (HIP
-    events around every launch on its stream)."""
+    events around every launch on its stream); with the algorithmic bytes per
+    launch (operands and targets, counted in the kernel) beside the
+    counter-measured HBM traffic, and the counter-measured matrix-core use."""
     launches = max(launches, 1)
     per_s = seconds / launches
     per_f = flops / launches
     tf = per_f / per_s / 1e12 if per_s > 0 else 0.0
     traffic = measured_traffic("accum", name)
-    return {"bound": "alu", "achieved": round(tf, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 6),
-            "traffic": round(traffic) if traffic is not None else None, "kernel": name, "launches": launches,
-            "mean_launch_ms": round(per_s * 1e3, 4), "flops_per_launch": per_f,
-            "total_seconds": round(seconds, 3)}
+    per_b = abytes / launches if abytes else None
+    out = {"bound": "alu", "achieved": round(tf, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 6),
+           "traffic": round(traffic) if traffic is not None else None, "kernel": name, "launches": launches,
+           "mean_launch_ms": round(per_s * 1e3, 4), "flops_per_launch": per_f,
+           "algorithmic_bytes_per_launch": round(per_b) if per_b else None,
+           "traffic_over_algorithmic": round(traffic / per_b, 3) if traffic is not None and per_b else None,
+           "total_seconds": round(seconds, 3)}
+    m = measured_mfma(name)
+    if m is not None:
+        out["mfma"] = {k: m[k] for k in ("mfma_util_pct", "mfma_tflops", "mfma_flops_per_launch") if k in m}
+    return out
 
 
 def apply_probe(count, n=127, eps=1e-4):
@@ -172,6 +201,39 @@ def traffic_record(record, fetch, write, cfetch, cwrite, copy_bytes, named, comm
         out["kernels"][name] = {"regex": regex, "dispatches": len(f), "units": units,
                                 "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
                                 "traffic_bytes_per_launch": fk * 1024.0 * ff + wk * 1024.0 * fw}
+    return out
+
+
+def mfma_record(csv_path, named, commands):
+    """Matrix-core use of each named kernel (name=regex) from one rocprofv3
+    --pmc pass of SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64 / _BF16 (matrix-core
+    operations / 512) and MfmaUtil (SQ_VALU_MFMA_BUSY_CYCLES over
+    GRBM_GUI_ACTIVE x SIMDs, percent): MFMA flops per launch, their rate
+    over the launch durations of the pass, and the duration-weighted busy
+    percentage."""
+    import csv
+    import re
+    rows = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            for name, regex in named:
+                if re.search(regex, r["Kernel_Name"]):
+                    d = rows.setdefault(name, {}).setdefault(r["Dispatch_Id"], {})
+                    d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                    d["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    out = {"source_sha256": kernel_source_hash(MFMA_RECORD[1]), "kernels": {}, "commands": commands}
+    for name, disp in rows.items():
+        n = len(disp)
+        mops = sum(d.get(c, 0.0) for d in disp.values()
+                   for c in ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+                             "SQ_INSTS_VALU_MFMA_MOPS_BF16"))
+        ns = sum(d["ns"] for d in disp.values())
+        util = sum(d.get("MfmaUtil", 0.0) * d["ns"] for d in disp.values()) / ns if ns else 0.0
+        k = {"dispatches": n, "mfma_flops_per_launch": mops * 512.0 / n,
+             "mean_launch_us_under_counters": ns / n / 1e3,
+             "mfma_tflops": round(mops * 512.0 / (ns * 1e-9) / 1e12, 4) if ns else None,
+             "mfma_util_pct": round(util, 4)}
+        out["kernels"][name] = k
     return out
 
 
@@ -302,7 +364,15 @@ def main():
                     metavar="RECORD FETCH WRITE COPY_FETCH COPY_WRITE COPY_BYTES name=regex[/K]",
                     help="print the calibrated traffic record of counter passes (RECORD: accum or apply); "
                          "the generating commands are read from stdin, one a line")
+    ap.add_argument("--mfma-record", nargs="+", metavar="CSV name=regex",
+                    help="print the matrix-core record of a rocprofv3 --pmc counter pass; the generating "
+                         "commands are read from stdin, one a line")
     args = ap.parse_args()
+    if args.mfma_record:
+        named = [tuple(x.split("=", 1)) for x in args.mfma_record[1:]]
+        cmds = [ln.rstrip("\n") for ln in sys.stdin if ln.strip()]
+        print(json.dumps(mfma_record(args.mfma_record[0], named, cmds), indent=1))
+        return
     if args.trace_summary:
         print(trace_summary(*args.trace_summary), end="")
         return
@@ -386,9 +456,9 @@ def main():
     # matrices and cores) and the accumulate-only kernel (FP32 products with
     # FP32 factors); `roofline` is the one with the larger total time
     kt = kernel_roofline("accum_kernel", st["accum_launches"], st["accum_seconds"], st["accum_flops"],
-                         FP64_VECTOR_PEAK_TFLOPS)
+                         FP64_VECTOR_PEAK_TFLOPS, st.get("accum_bytes"))
     kd = kernel_roofline("accum_dense_kernel", st["dense_launches"], st["dense_seconds"], st["dense_flops"],
-                         FP32_VECTOR_PEAK_TFLOPS)
+                         FP32_VECTOR_PEAK_TFLOPS, st.get("dense_bytes"))
     roof, roof2 = (kt, kd) if st["accum_seconds"] >= st["dense_seconds"] else (kd, kt)
     out = {"metric": METRIC, "value": round(t_mixed, 3), "unit": "s", "n_gpus": 1, "steps": len(mixed),
            "warmup": warm, "steps_requested": args.steps, "warmup_requested": args.warmup,

@@ -189,6 +189,12 @@ typedef struct {
                                               row segment by row segment (its dense leaves and U
                                               factors) for the row kernel; part of
                                               bytes_allocated, not of bytes_factors */
+    /* algorithmic bytes of the two H-arithmetic kernels (with ACR_KERNEL_TIMING=1), summed
+       over their launches: every operand entry a piece product reads (factor rows, leaf
+       blocks; once per product), each target's old value or dense sum read and its result
+       written, at storage precision; scratch traffic is not counted */
+    double accum_bytes;
+    double dense_bytes;
 } acr_stats_t;
 
 typedef struct acr_handle acr_handle;

@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("dense_seconds", ctypes.c_double), ("dense_flops", ctypes.c_double),
                 ("bytes_peak", ctypes.c_double), ("bytes_level", ctypes.c_double * MAX_LEVELS),
                 ("level_seconds", ctypes.c_double * MAX_LEVELS), ("setup_flops_class", ctypes.c_double * 4),
-                ("leaf_inverse_flops", ctypes.c_double), ("bytes_apply_image", ctypes.c_double)]
+                ("leaf_inverse_flops", ctypes.c_double), ("bytes_apply_image", ctypes.c_double),
+                ("accum_bytes", ctypes.c_double), ("dense_bytes", ctypes.c_double)]
 
     def as_dict(self):
         lv = self.levels
@@ -82,7 +83,8 @@ class Stats(ctypes.Structure):
                 "bytes_peak": self.bytes_peak, "bytes_level": list(self.bytes_level[:lv]),
                 "level_seconds": list(self.level_seconds[:lv]),
                 "setup_flops_class": dict(zip(("products", "gram", "core", "rebuild"), self.setup_flops_class)),
-                "leaf_inverse_flops": self.leaf_inverse_flops, "bytes_apply_image": self.bytes_apply_image}
+                "leaf_inverse_flops": self.leaf_inverse_flops, "bytes_apply_image": self.bytes_apply_image,
+                "accum_bytes": self.accum_bytes, "dense_bytes": self.dense_bytes}
 
 
 class Factor(ctypes.Structure):

@@ -527,6 +527,8 @@ acr_status acr_stats(const acr_handle* h, acr_stats_t* st) {
     for (int c = 0; c < 4; ++c) st->setup_flops_class[c] += o.setup_flops_class[c];
     st->leaf_inverse_flops += o.leaf_inverse_flops;
     st->bytes_apply_image += o.bytes_apply_image;
+    st->accum_bytes += o.accum_bytes;
+    st->dense_bytes += o.dense_bytes;
     st->levels = std::max(st->levels, o.levels);
     for (int r = 0; r < ACR_MAX_LEVELS; ++r) {
       st->bytes_level[r] += o.bytes_level[r];

@@ -63,7 +63,7 @@ void Handle::setup(const acr_problem* ps, int count, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     for (void* b : cap_pool) dfree(b);
     cap_pool.clear();
-    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * FC_COUNT * sizeof(double), s));
+    if (d_flops) HIPCHK(hipMemsetAsync(d_flops, 0, 2 * (FC_COUNT + 1) * sizeof(double), s));
     leaf_inverse_flops = 0.0;
     accum_launches = dense_launches = 0;
     ev_used = 0;
@@ -90,8 +90,8 @@ void Handle::prepare(const acr_problem* ps, int count, hipStream_t s) {
   HIPCHK(hipMemsetAsync(d_flags, 0, FL_COUNT * sizeof(int32_t), s));
   if (const char* e = getenv("ACR_KERNEL_TIMING"); e && e[0] == '1') {
     timing = true;
-    d_flops = dnew<double>(2 * FC_COUNT);
-    HIPCHK(hipMemsetAsync(d_flops, 0, 2 * FC_COUNT * sizeof(double), s));
+    d_flops = dnew<double>(2 * (FC_COUNT + 1));
+    HIPCHK(hipMemsetAsync(d_flops, 0, 2 * (FC_COUNT + 1) * sizeof(double), s));
   }
   if (const char* e = getenv("ACR_PROFILE"); e && e[0] == '1') {
     d_prof = dnew<unsigned long long>(PS_COUNT);
@@ -229,15 +229,18 @@ void Handle::finish(hipStream_t s, std::chrono::steady_clock::time_point t_start
         fclose(f);
       }
     }
-    // [kernel][class]: the truncating kernel, then the accumulate-only one
-    double fl[2 * FC_COUNT] = {0.0};
+    // [kernel][flops by class, bytes]: the truncating kernel, then the accumulate-only one
+    constexpr int W = FC_COUNT + 1;
+    double fl[2 * W] = {0.0};
     HIPCHK(hipMemcpy(fl, d_flops, sizeof(fl), hipMemcpyDeviceToHost));
     st.accum_flops = st.dense_flops = 0.0;
     for (int c = 0; c < FC_COUNT; ++c) {
       st.accum_flops += fl[c];
-      st.dense_flops += fl[FC_COUNT + c];
-      st.setup_flops_class[c] = fl[c] + fl[FC_COUNT + c];
+      st.dense_flops += fl[W + c];
+      st.setup_flops_class[c] = fl[c] + fl[W + c];
     }
+    st.accum_bytes = fl[FC_COUNT];
+    st.dense_bytes = fl[W + FC_COUNT];
     st.setup_flops = st.accum_flops + st.dense_flops + leaf_inverse_flops;
   }
   if (d_prof) {

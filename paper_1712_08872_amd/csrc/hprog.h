@@ -85,7 +85,7 @@ struct AccumArgs {
   int32_t mode;                // truncating kernel: 0 every low-rank target, 1 all but the dense
                                // sums, 2 the dense sums only
   unsigned long long* prof;    // optional cycle counters (null = off)
-  double* flops;               // optional algorithmic flop counters by FlopClass (null = off)
+  double* flops;               // optional counters (null = off): flops by FlopClass, then algorithmic bytes
   int32_t bf16_products;       // 1: the matrix-core piece products take BF16 operands (rounded to
                                // nearest even) with FP32 accumulation (FP32 factors, eps >= 1e-2)
 };

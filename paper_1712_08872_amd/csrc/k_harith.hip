@@ -124,6 +124,7 @@ struct Lds {
   int ival[8];
   double dval[4];
   double flops[FC_COUNT];  // algorithmic flops of the block's items by class (thread 0)
+  double bytes;            // algorithmic operand and target bytes of the block's items (thread 0)
 };
 
 // LDS of the accumulate-only kernel: the staging tiles of the piece
@@ -134,11 +135,17 @@ struct LdsPiece {
   CT S1[KC * LDM];
   CT S2[KC * LDM];
   double flops[FC_COUNT];
+  double bytes;
 };
 
 #define FLOP(L_, c_, x_)                    \
   do {                                      \
     if (threadIdx.x == 0) (L_).flops[c_] += (double)(x_); \
+  } while (0)
+// algorithmic bytes, counted only when the counters are on
+#define BYTES(A_, L_, x_)                                     \
+  do {                                                        \
+    if ((A_).flops && threadIdx.x == 0) (L_).bytes += (double)(x_); \
   } while (0)
 
 // Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
@@ -849,6 +856,7 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
     FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + nc));
+    BYTES(A, L, (double)kl * (nq + nc) * sizeof(T));
   } else {
     for (int idx = tid; idx < nc * take; idx += TPB) {
       const int cc = idx / take, jj = idx - cc * take;
@@ -857,6 +865,7 @@ __device__ bool lrx_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       Vs[(int64_t)(cA - tc.c0 + cc) * KC + K + jj] = (T)s;
     }
     FLOP(L, FC_PRODUCT, 2.0 * nq * nc * take);
+    BYTES(A, L, (double)nq * nc * sizeof(T));
   }
   return true;
 }
@@ -923,6 +932,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
     FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + nr));
+    BYTES(A, L, (double)kl * (nq + nr) * sizeof(T));
   } else {
     for (int idx = tid; idx < nr * take; idx += TPB) {
       const int r = idx / take, jj = idx - r * take;
@@ -931,6 +941,7 @@ __device__ bool lry_single(const AccumArgs<T>& A, const Piece& P, const DLeaf& t
       Us[(int64_t)(rA - tc.r0 + r) * KC + K + jj] = (T)(alpha * s);
     }
     FLOP(L, FC_PRODUCT, 2.0 * nq * nr * take);
+    BYTES(A, L, (double)nq * nr * sizeof(T));
   }
   return true;
 }
@@ -957,6 +968,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const LeafRef<T> xr = leaf_ref(A, xi, P.xleaf, x);
     const T* Ux = xr.U;
     const T* Vx = xr.V;
+    BYTES(A, L, (double)take * ((P.wr1 - P.wr0) + x.n) * sizeof(T));  // U_x window rows, V_x
     if (lrx_single(A, P, tc, x, xr, yi, j0, take, Us, Vs, K, L)) {
       __syncthreads();
       PROF_ADD(PS_LRX, clock64() - tpc);
@@ -990,6 +1002,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           tn_product<T, BF>(lp + (q0 - lam.r0) + (int64_t)(c0 - lam.c0) * lr.ldu, lr.ldu, vx, xr.ldv, nq, nc, take,
                             S0c, S1c, S2c, A.prof);
           FLOP(L, FC_PRODUCT, 2.0 * nq * nc * take);
+          BYTES(A, L, (double)nq * nc * sizeof(T));
           for (int idx = tid; idx < nc * take; idx += TPB) {
             const int cc = idx / take, jj = idx - cc * take;
             T* d = &Vs[(int64_t)(c0 + cc - tc.c0) * KC + K + jj];
@@ -1006,6 +1019,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         nn_acc(Vl + (cA - lam.c0), lr.ldv, cB - cA, kl, S0c, take, Vs + (int64_t)(cA - tc.c0) * KC + K, KC, 1, 1.0,
                S1c, A.prof);
         FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (cB - cA)));
+        BYTES(A, L, (double)kl * (nq + (cB - cA)) * sizeof(T));
       }
     }
   } else if (P.kind == PK_LRY) {
@@ -1014,6 +1028,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
     const LeafRef<T> yr = leaf_ref(A, yi, P.yleaf, y);
     const T* Uy = yr.U;
     const T* Vy = yr.V;
+    BYTES(A, L, (double)take * ((P.wc1 - P.wc0) + y.m) * sizeof(T));  // V_y window columns, U_y
     if (lry_single(A, P, tc, y, yr, xi, j0, take, Us, Vs, K, L)) {
       __syncthreads();
       PROF_ADD(PS_LRY, clock64() - tpc);
@@ -1051,6 +1066,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
           nn_acc(lp + (rA - lam.r0) + (int64_t)(q0 + qc - lam.c0) * lr.ldu, lr.ldu, rB - rA, nqc, S0c, take,
                  Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
           FLOP(L, FC_PRODUCT, 2.0 * (rB - rA) * nqc * take);
+          BYTES(A, L, (double)(rB - rA) * nqc * sizeof(T));
         }
       } else {
         const int kl = rank_of(A, xi, l);
@@ -1061,6 +1077,7 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
         nn_acc(Ul + (rA - lam.r0), lr.ldu, rB - rA, kl, S0c, take, Us + (int64_t)(rA - tc.r0) * KC + K, KC, 1, alpha,
                S1c, A.prof);
         FLOP(L, FC_PRODUCT, 2.0 * kl * take * (nq + (rB - rA)));
+        BYTES(A, L, (double)kl * (nq + (rB - rA)) * sizeof(T));
       }
     }
   } else if (P.kind == PK_DD) {
@@ -1090,8 +1107,10 @@ __device__ void piece_columns(const AccumArgs<T>& A, int b, const Piece& P, cons
       nn_acc(xp + (P.wr0 - x.r0) + (int64_t)(qc - x.c0) * xr.ldu, xr.ldu, P.wr1 - P.wr0, nqc, S0c, take,
              Us + (int64_t)(P.wr0 - tc.r0) * KC + K, KC, 1, alpha, S1c, A.prof);
       FLOP(L, FC_PRODUCT, 2.0 * (P.wr1 - P.wr0) * nqc * take);
+      BYTES(A, L, (double)((P.wr1 - P.wr0) + take) * nqc * sizeof(T));  // x block, y columns
     }
   } else {  // PK_COPY of a low-rank leaf
+    BYTES(A, L, (double)take * (m + n) * sizeof(T));
     const int si = inst_of(A, b, P.xrole);
     const DLeaf s = A.leaves[P.xleaf];
     const LeafRef<T> sr = leaf_ref(A, si, P.xleaf, s);
@@ -1200,6 +1219,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       const T* xp = xr.U;
       const T* yp = yr.U;
       const int M0 = imax(x.c0, y.r0), M1 = imin(x.c0 + x.n, y.r0 + y.m);
+      BYTES(A, L, (double)imax(M1 - M0, 0) * ((P.wr1 - P.wr0) + (P.wc1 - P.wc0)) * sizeof(T));  // the two blocks
       for (int cc0 = P.wc0; cc0 < P.wc1; cc0 += KC) {
         const int nc = imin(KC, P.wc1 - cc0);
         for (int qc = M0; qc < M1; qc += KC) {
@@ -1219,6 +1239,7 @@ __device__ void dense_pieces(const AccumArgs<T>& A, int b, const Target& tg, con
       ++p;
       const int si = inst_of(A, b, P.xrole);
       if (si < 0) continue;
+      BYTES(A, L, (double)tc.m * tc.n * sizeof(T));  // the source leaf
       const LeafRef<T> sr = leaf_ref(A, si, P.xleaf, A.leaves[P.xleaf]);
       const T* src = sr.U;
       const double* rho = P.rv >= 0 ? A.vec_ptr[b * A.nvroles + P.rv] : nullptr;
@@ -1262,8 +1283,10 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
   unsigned long long* prof = A.prof;
-  if (tid == 0)
+  if (tid == 0) {
     for (int c = 0; c < FC_COUNT; ++c) L.flops[c] = 0.0;
+    L.bytes = 0.0;
+  }
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
     const int t = A.t0 + item % A.nt;
@@ -1305,6 +1328,7 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
         Vc[idx] = (T)v;
       }
       if (tid == 0) *rk = ks;
+      BYTES(A, L, 2.0 * (tc.m + tc.n) * ks * sizeof(T));
       __syncthreads();
       continue;
     }
@@ -1385,6 +1409,9 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
     if (dacc || tg.p1 > tg.p0 || !tg.beta) {
       int k = truncate_block<T, BF>(Us, Vs, tc.m, tc.n, K, A.eps, L, A.flags, A.prof);
       int kw = imin(k, tc.cap);
+      // the dense sum or the old factors read, the truncated factors written
+      BYTES(A, L, ((double)(tc.m + tc.n) * kw +
+                   (dacc ? (double)tc.m * tc.n : (tg.beta ? (double)(tc.m + tc.n) * k0 : 0.0))) * sizeof(T));
       if (tid == 0) {
         if (k > tc.cap) atomicOr(&A.flags[FL_RANK_OVERFLOW], 1);
         atomicMax(&A.flags[FL_MAXRANK], k);
@@ -1401,8 +1428,10 @@ __global__ __launch_bounds__(TPB) ACCUM_OCCUPANCY void accum_kernel(AccumArgs<T>
     }
     __syncthreads();
   }
-  if (tid == 0 && A.flops)
+  if (tid == 0 && A.flops) {
     for (int c = 0; c < FC_COUNT; ++c) atomicAdd(A.flops + c, L.flops[c]);
+    atomicAdd(A.flops + FC_COUNT, L.bytes);
+  }
 }
 
 // The accumulate-only kernel needs only the staging tiles (FP32 tiles for
@@ -1428,8 +1457,10 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
   const int tid = threadIdx.x;
   const int total = A.nbatch * A.nt;
   T* Us = A.scratch + (int64_t)blockIdx.x * A.scratch_stride;
-  if (tid == 0)
+  if (tid == 0) {
     for (int c = 0; c < FC_COUNT; ++c) L.flops[c] = 0.0;
+    L.bytes = 0.0;
+  }
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int b = item / A.nt;
     const int t = A.t0 + item % A.nt;
@@ -1446,36 +1477,39 @@ __global__ __launch_bounds__(TPB) DENSE_OCCUPANCY void accum_dense_kernel(AccumA
     T* Vs = Us + (int64_t)tc.m * KC;
     unsigned long long* prof = A.prof;
     const long long t_item = clock64();
+    T* dst = C;  // the dense leaf itself, or the dense sum of a low-rank leaf
     if (tc.fmt == 0) {
       if (!tg.beta)
         for (int idx = tid; idx < tc.m * tc.n; idx += TPB) C[idx] = (T)0;
+      BYTES(A, L, (tg.beta ? 2.0 : 1.0) * tc.m * tc.n * sizeof(T));  // the leaf read (accumulated into), written
+    } else {
+      if (tid == 0) wsum = 0;
       __syncthreads();
-      dense_pieces<BF>(A, b, tg, tc, C, Us, Vs, L);
-      PROF_ADD(PS_DENSE, clock64() - t_item);
-      continue;
+      for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&wsum, piece_width(A, b, A.pieces[p]));
+      __syncthreads();
+      if (!(wsum > imin(tc.m, tc.n))) continue;
+      dst = A.dbuf + (int64_t)b * A.dstride + A.doff[t];
+      const int k0 = tg.beta ? A.inst_rank[ci][tg.cleaf] : 0;
+      const T* Uc = C;
+      const T* Vc = C + (int64_t)tc.m * tc.cap;
+      for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
+        const int i = idx % tc.m, c = idx / tc.m;
+        double v = 0.0;
+        for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
+        dst[idx] = (T)v;
+      }
+      FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * k0);
+      BYTES(A, L, ((double)(tc.m + tc.n) * k0 + (double)tc.m * tc.n) * sizeof(T));  // old factors read, sum written
     }
-    if (tid == 0) wsum = 0;
     __syncthreads();
-    for (int p = tg.p0 + tid; p < tg.p1; p += TPB) atomicAdd(&wsum, piece_width(A, b, A.pieces[p]));
-    __syncthreads();
-    if (!(wsum > imin(tc.m, tc.n))) continue;
-    T* D = A.dbuf + (int64_t)b * A.dstride + A.doff[t];
-    const int k0 = tg.beta ? A.inst_rank[ci][tg.cleaf] : 0;
-    const T* Uc = C;
-    const T* Vc = C + (int64_t)tc.m * tc.cap;
-    for (int idx = tid; idx < tc.m * tc.n; idx += TPB) {
-      const int i = idx % tc.m, c = idx / tc.m;
-      double v = 0.0;
-      for (int j = 0; j < k0; ++j) v += (double)Uc[i + (int64_t)j * tc.m] * (double)Vc[c + (int64_t)j * tc.n];
-      D[idx] = (T)v;
-    }
-    FLOP(L, FC_PRODUCT, 2.0 * tc.m * tc.n * k0);
-    __syncthreads();
-    dense_pieces<BF>(A, b, tg, tc, D, Us, Vs, L);
-    PROF_ADD(PS_DACC, clock64() - t_item);
+    // one call site, so that the product code is inlined once
+    dense_pieces<BF>(A, b, tg, tc, dst, Us, Vs, L);
+    PROF_ADD(tc.fmt == 0 ? PS_DENSE : PS_DACC, clock64() - t_item);
   }
-  if (tid == 0 && A.flops)
+  if (tid == 0 && A.flops) {
     for (int c = 0; c < FC_COUNT; ++c) atomicAdd(A.flops + c, L.flops[c]);
+    atomicAdd(A.flops + FC_COUNT, L.bytes);
+  }
 }
 
 // ------------------------------------------------------------ launchers

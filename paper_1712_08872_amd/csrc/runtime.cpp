@@ -404,7 +404,7 @@ void Handle::run_accum_step(Program& P, const Step& st, int nbatch, int nroles, 
         kc64::launch_accum<T>(a1, grid, s2);
     }, "");
     AccumArgs<T> ad = a;
-    ad.flops = d_flops ? d_flops + FC_COUNT : nullptr;
+    ad.flops = d_flops ? d_flops + FC_COUNT + 1 : nullptr;
     timed(s, [&] {
       if (kc == 38)
         kc38::launch_accum_dense<T>(ad, grid, s);
