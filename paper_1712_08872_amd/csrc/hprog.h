@@ -17,7 +17,10 @@ namespace acr {
 
 constexpr int KC_MAX = 64;     // widest low-rank accumulation round the kernels support
 constexpr int TPB = 256;       // threads per block of the H-arithmetic kernels
-constexpr int DACC_ELEMS = 16384;  // low-rank targets with m*n up to this may be accumulated densely
+#ifndef ACR_DACC_ELEMS
+#define ACR_DACC_ELEMS 16384
+#endif
+constexpr int DACC_ELEMS = ACR_DACC_ELEMS;  // low-rank targets with m*n up to this may be accumulated densely
 
 enum PieceKind : int32_t {
   PK_LRX = 0,   // x low-rank A-leaf times a B-region (list): rank k_x

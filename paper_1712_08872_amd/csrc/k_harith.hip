@@ -110,7 +110,10 @@ __device__ __forceinline__ void rr_pair(int Kp, int r, int i, int& p, int& q) {
   q = ((Kp - 2 - i + r) % M) + 1;
 }
 
-constexpr int ROUND = 32;  // columns appended between recompressions
+#ifndef ACR_ROUND
+#define ACR_ROUND 32
+#endif
+constexpr int ROUND = ACR_ROUND;  // columns appended between recompressions
 constexpr int DACC_MAX = DACC_ELEMS;  // largest m*n of a low-rank target accumulated densely
 constexpr int LDM = KC + 1;  // padded leading dimension of the K x K matrices (no LDS bank conflicts)
 
