@@ -41,7 +41,7 @@ def _has_coupling(perm, nx, r0, c0, m, n):
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
-@pytest.mark.parametrize("eta", [1.0, 2.0, 4.0, 8.0])
+@pytest.mark.parametrize("eta", [1.0, 2.0, 4.0, 8.0, 256.0])
 def test_geometry_equals_oracle(shape, eta):
     nx, ny = shape
     leaf = 32

@@ -38,6 +38,9 @@ CASES = {
     "convdiff15": ("convdiff", 15, 15, 15, 1e-5, 2.0, 32),
     "helmholtz11": ("helmholtz", 11, 11, 11, 1e-6, 1.0, 16),
     "poisson_eta4": ("poisson", 17, 14, 9, 1e-6, 4.0, 16),
+    # eta = 256: every separated block pair admissible (the weak end of the
+    # admissibility study of Sec. 4.2)
+    "poisson_eta256": ("poisson", 17, 14, 9, 1e-6, 256.0, 16),
     # eps = 1e-4 selects the narrow (38-column) accumulation rounds
     "poisson15_e4": ("poisson", 15, 15, 15, 1e-4, 2.0, 32),
     "convdiff_ragged_e4": ("convdiff", 14, 11, 9, 1e-4, 2.0, 16),
