@@ -14,7 +14,8 @@
 // accuracy, singular values sigma_i > eps sigma_1 kept) of a block given as
 // U V^T with K columns (the block's current factors concatenated with the
 // incoming contributions): the column pairs are norm-balanced, the Gram
-// matrices G_U = U^T U and G_V = V^T V are formed in FP64, each is factored
+// matrices G_U = U^T U and G_V = V^T V are formed in FP64 (on the FP64
+// matrix cores, like the final product with the factors), each is factored
 // by Cholesky with symmetric pivoting, stopped at its numerical rank
 // (G = P R^T R P^T, so U = Q_U R_U P^T with Q_U = U_piv R_U11^-1); the
 // small core C = R_U P_U^T P_V R_V^T is reduced by Cholesky with symmetric
@@ -151,63 +152,102 @@ struct LdsPiece {
     if ((A_).flops && threadIdx.x == 0) (L_).bytes += (double)(x_); \
   } while (0)
 
-// Gram matrix G = X^T X of the first K columns of a row-major (ld KC)
-// matrix with `rows` rows, accumulated in FP64 into G (ld KC).  `tile` is
-// an LDS staging buffer of KC x KC doubles.
+// The tall products of a truncation on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16],
+// accumulator element r of lane l is row l / 16 + 4 r, column l % 16), the
+// operands read straight from the scratch, no LDS staging and no barrier
+// inside.  Both factors of the block at once, so that all four wavefronts
+// have work.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// G_U = U^T U and G_V = V^T V of the first K columns (U: m rows, V: n rows,
+// row-major ld KC) into GU, GV (LDS, ld LDM): 16 x 16 tiles of the upper
+// triangles over the wavefronts, 4 rows per step, mirrored below the
+// diagonal tiles.
 template <typename T>
-__device__ void gram(const T* X, int rows, int K, double* G, double* tile) {
-  const int tid = threadIdx.x;
-  constexpr int PER = (KC * KC + TPB - 1) / TPB;
-  double acc[PER];
-#pragma unroll
-  for (int e = 0; e < PER; ++e) acc[e] = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += KC) {
-    int nr = imin(KC, rows - r0);
-    for (int idx = tid; idx < KC * KC; idx += TPB) {
-      int rr = idx / KC, j = idx - rr * KC;
-      tile[idx] = (rr < nr && j < K) ? (double)X[(int64_t)(r0 + rr) * KC + j] : 0.0;
+__device__ void gram2(const T* U, int m, const T* V, int n, int K, double* GU, double* GV) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int nt = (K + 15) >> 4, nu = nt * (nt + 1) / 2;
+  for (int u = w; u < 2 * nu; u += TPB / 64) {
+    const bool second = u >= nu;
+    const T* X = second ? V : U;
+    const int rows = second ? n : m;
+    double* G = second ? GV : GU;
+    int ti = 0, rem = second ? u - nu : u;
+    while (rem >= nt - ti) {
+      rem -= nt - ti;
+      ++ti;
     }
-    __syncthreads();
+    const int tj = ti + rem;
+    const int ci = ti * 16 + l16, cj = tj * 16 + l16;
+    const bool ai = ci < K, bj = cj < K;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int r0 = 0; r0 < rows; r0 += 4) {
+      const int row = r0 + g;
+      const bool in = row < rows;
+      const double a = (ai && in) ? (double)X[(int64_t)row * KC + ci] : 0.0;
+      const double b = (bj && in) ? (double)X[(int64_t)row * KC + cj] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      int idx = tid + e * TPB;
-      int i = idx / KC, j = idx - i * KC;
+    for (int r = 0; r < 4; ++r) {
+      const int i = ti * 16 + g + 4 * r, j = cj;
       if (i < K && j < K) {
-        double s = 0.0;
-        for (int rr = 0; rr < nr; ++rr) s += tile[rr * KC + i] * tile[rr * KC + j];
-        acc[e] += s;
+        G[i * LDM + j] = acc[r];
+        if (ti != tj) G[j * LDM + i] = acc[r];  // a diagonal tile holds both halves itself
       }
     }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    int idx = tid + e * TPB;
-    int i = idx / KC, j = idx - i * KC;
-    if (i < K && j < K) G[i * LDM + j] = acc[e];
   }
   __syncthreads();
 }
 
-// In place X[:, 0:k] = X[:, 0:K] R (row-major ld KC, R is K x k in LDS ld KC).
+// In place U[:, 0:k] = U[:, 0:K] RU and V[:, 0:k] = V[:, 0:K] RV (RU, RV:
+// K x k in LDS, ld LDM): a wavefront owns 16 rows and forms all their k
+// columns (at most four 16-column tiles) before it writes any of them.
 template <typename T>
-__device__ void rebuild(T* X, int rows, int K, int k, const double* R, double* tile) {
-  const int tid = threadIdx.x;
-  for (int r0 = 0; r0 < rows; r0 += KC) {
-    int nr = imin(KC, rows - r0);
-    for (int idx = tid; idx < KC * KC; idx += TPB) {
-      int rr = idx / KC, j = idx - rr * KC;
-      tile[idx] = (rr < nr && j < K) ? (double)X[(int64_t)(r0 + rr) * KC + j] : 0.0;
+__device__ void rebuild2(T* U, int m, T* V, int n, int K, int k, const double* RU, const double* RV) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int nct = (k + 15) >> 4;
+  const int nbu = (m + 15) >> 4, nb = nbu + ((n + 15) >> 4);
+  for (int u = w; u < nb; u += TPB / 64) {
+    const bool second = u >= nbu;
+    T* X = second ? V : U;
+    const int rows = second ? n : m;
+    const double* R = second ? RV : RU;
+    const int rb = (second ? u - nbu : u) * 16;
+    const int row = rb + l16;
+    const bool rin = row < rows;
+    f64x4 acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int a0 = 0; a0 < K; a0 += 4) {
+      const int a = a0 + g;
+      const bool kin = a < K;
+      const double av = (rin && kin) ? (double)X[(int64_t)row * KC + a] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        if (ct < nct) {
+          const int c = ct * 16 + l16;
+          const double bv = (kin && c < k) ? R[a * LDM + c] : 0.0;
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+        }
+      }
     }
-    __syncthreads();
-    for (int idx = tid; idx < nr * k; idx += TPB) {
-      int rr = idx / k, c = idx - rr * k;
-      double s = 0.0;
-      for (int i = 0; i < K; ++i) s += tile[rr * KC + i] * R[i * LDM + c];
-      X[(int64_t)(r0 + rr) * KC + c] = (T)s;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (ct < nct) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rb + g + 4 * r, c = ct * 16 + l16;
+          if (i < rows && c < k) X[(int64_t)i * KC + c] = (T)acc[ct][r];
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Ordering point inside one wavefront: the LDS accesses of a wavefront are
@@ -378,8 +418,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   long long t0 = clock64();
   PROF_ADD(PS_TRUNC, 1);
   PROF_ADD(PS_KSUM, K);
-  gram(Us, m, K, L.S2, L.S1);
-  gram(Vs, n, K, L.S0, L.S1);
+  gram2(Us, m, Vs, n, K, L.S2, L.S0);
   FLOP(L, FC_GRAM, (double)(m + n) * K * (K + 1));
   long long t1 = clock64();
   PROF_ADD(PS_GRAM, t1 - t0);
@@ -582,8 +621,7 @@ __device__ int truncate_block(T* Us, T* Vs, int m, int n, int K, double eps, Lds
   __syncthreads();
   long long t3 = clock64();
   PROF_ADD(PS_EIG2, t3 - t2);
-  rebuild(Us, m, K, k, L.S2, L.S1);
-  rebuild(Vs, n, K, k, L.S0, L.S1);
+  rebuild2(Us, m, Vs, n, K, k, L.S2, L.S0);
   FLOP(L, FC_REBUILD, (double)k * (rU * rU + rV * rV) + 2.0 * (m + n) * K * k);
   PROF_ADD(PS_REBUILD, clock64() - t3);
   return k;
