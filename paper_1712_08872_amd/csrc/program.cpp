@@ -251,6 +251,19 @@ void StepBuilder::finish_step() {
   }
   P.max_m = std::max(P.max_m, st.max_m);
   P.max_n = std::max(P.max_n, st.max_n);
+  // Longest targets first: the blocks of a launch take targets in order, so
+  // a long one (a large low-rank leaf fed by long leaf lists) that came last
+  // would run alone at the end of the step.  The estimate is the target's
+  // border (m + n) times its pieces and their list leaves; targets are
+  // independent, so the order changes no result.
+  auto cost = [&](const Target& T) {
+    const Leaf& L = G.lf[T.cleaf];
+    int64_t w = 0;
+    for (int p = T.p0; p < T.p1; ++p) w += 1 + (P.pieces[p].l1 - P.pieces[p].l0);
+    return (int64_t)(L.m + L.n) * w;
+  };
+  std::stable_sort(P.targets.begin() + st.t0, P.targets.begin() + st.t0 + st.nt,
+                   [&](const Target& a, const Target& b) { return cost(a) > cost(b); });
   if (st.nt > 0) P.steps.push_back(st);
   step_t0_ = -1;
 }
