@@ -84,7 +84,10 @@ def test_dense_cr_constant_kappa_mode_recurrence():
     np.testing.assert_allclose(np.diag(Q2.T @ Dinv @ Q2), 1.0 / d, rtol=1e-10)
 
 
-@pytest.mark.parametrize("dims,kind", [((15, 15, 15), "poisson"), ((13, 9, 6), "poisson"), ((13, 9, 6), "recirc")])
+# (31, 31, 7): the plane geometry of the 31^3 workload (961-point planes,
+# several cluster levels, leaf 16) over three reduction levels
+@pytest.mark.parametrize("dims,kind", [((15, 15, 15), "poisson"), ((13, 9, 6), "poisson"), ((13, 9, 6), "recirc"),
+                                       ((31, 31, 7), "poisson")])
 def test_hacr_eps_to_zero_matches_exact_cr(dims, kind):
     nx, ny, nz = dims
     S, A = _problem(kind, nx, ny, nz, seed=3)
