@@ -59,11 +59,11 @@ def test_dense_cr_reduced_system_is_schur_complement():
                                    rtol=1e-9, atol=1e-12)
 
 
-def test_dense_cr_constant_kappa_mode_recurrence():
+@pytest.mark.parametrize("n,nz", [(5, 15), (15, 31), (31, 63)])
+def test_dense_cr_constant_kappa_mode_recurrence(n, nz):
     """Constant kappa, nz = 2^K - 1: every block is diagonal in the 2D
     DST basis; per mode d_{r+1} = d_r - 2 c_r^2/d_r, c_{r+1} = -c_r^2/d_r."""
-    nx = ny = 5
-    nz = 15
+    nx = ny = n
     S = assembly.stencil7("poisson", nx, ny, nz)
     cr = dense_cr.DenseCR(*assembly.plane_blocks(S, nx, ny, nz))
     hx = 1.0 / (nx + 1)
